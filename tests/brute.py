@@ -1,0 +1,106 @@
+"""Brute-force point sets from the paper's unreduced definitions (tiny m only).
+
+Independent of the C oracle: exact rational arithmetic with Python integers
+and Fractions, explicit digit vectors, explicit F_2 matrices and polynomials.
+Used to pin the oracle's point tables.
+
+  lattice      Sec. 1.1 / 1.3: x_k = {k z / N}, z_j = b^{w_j} z'_j
+  polynomial   Sec. 1.1: x_k = nu(k(x) g_j(x) / x^m), g_j = x^{w_j} g'_j
+  digital net  eq. def:digital with the reduced matrices of eq.
+               reduced_genmat_net2: last min(w_j, m) rows of C^{(j)} set to 0
+"""
+from __future__ import annotations
+
+from fractions import Fraction
+
+import numpy as np
+from scipy.special import ndtri
+
+from paper_2305_11645_amd.inputs import (DIGITAL_NET, DIGITAL_SHIFT, LATTICE, MAP_CENTER,
+                                         MAP_INVNORM, MAP_TENT, POLY_LATTICE, RANDOM_SHIFT)
+
+
+def digits(n: int, m: int) -> list[int]:
+    """b-adic digits of n, least significant first (b = 2)."""
+    return [(n >> q) & 1 for q in range(m)]
+
+
+def net_matrix(wl, j: int) -> list[list[int]]:
+    """C^{(j)} as an m x m 0/1 matrix: row p-1 = output digit p, column q-1 = input digit q."""
+    m = wl.m
+    C = [[0] * m for _ in range(m)]
+    for q in range(m):
+        word = int(wl.gen[j * m + q])
+        for p in range(m):
+            C[p][q] = (word >> p) & 1
+    return C
+
+
+def reduced_net_matrix(wl, j: int) -> list[list[int]]:
+    m = wl.m
+    C = net_matrix(wl, j)
+    keep = m - min(int(wl.w[j]), m)
+    for p in range(keep, m):
+        C[p] = [0] * m
+    return C
+
+
+def poly_mul_mod2(a: list[int], b: list[int]) -> list[int]:
+    out = [0] * (len(a) + len(b))
+    for i, ai in enumerate(a):
+        if ai:
+            for k, bk in enumerate(b):
+                out[i + k] ^= bk
+    return out
+
+
+def unshifted_value(wl, k: int, j: int) -> Fraction:
+    """The unreduced point definition, as an exact fraction in [0, 1)."""
+    m, N = wl.m, 1 << wl.m
+    w = int(wl.w[j])
+    if wl.kind == LATTICE:
+        z = (2 ** w) * int(wl.gen[j])
+        return Fraction((k * z) % N, N)
+    if wl.kind == POLY_LATTICE:
+        gp = digits(int(wl.gen[j]), 64)
+        g = [0] * w + gp                           # x^{w_j} g'_j(x)
+        f = poly_mul_mod2(digits(k, m), g)[:m]     # k(x) g_j(x) mod x^m
+        return sum((Fraction(f[i], 2 ** (m - i)) for i in range(m)), Fraction(0))
+    C = reduced_net_matrix(wl, j)
+    n = digits(k, m)
+    y = [sum(C[p][q] * n[q] for q in range(m)) % 2 for p in range(m)]
+    return sum((Fraction(y[p], 2 ** (p + 1)) for p in range(m)), Fraction(0))
+
+
+def digital_shift(x: Fraction, delta: int) -> float:
+    """Digit-wise XOR of the first 52 digits; the tail is replaced by its midpoint 2^-53."""
+    assert x.denominator & (x.denominator - 1) == 0 and x.denominator <= 2 ** 52
+    xd = [int((x * 2 ** (p + 1)) % 2 >= 1) for p in range(52)]     # digit p+1 of x
+    sd = [(delta >> (51 - p)) & 1 for p in range(52)]              # digit p+1 of delta / 2^52
+    val = sum((Fraction(xd[p] ^ sd[p], 2 ** (p + 1)) for p in range(52)), Fraction(0))
+    return float(val + Fraction(1, 2 ** 53))
+
+
+def value(wl, r: int, k: int, j: int) -> float:
+    """Point k, coordinate j, shift r, after the map (FP64)."""
+    x = unshifted_value(wl, k, j)
+    if wl.rand == DIGITAL_SHIFT:
+        v = digital_shift(x, int(wl.dshift[r, j]))
+    else:
+        v = float(x)
+        if wl.rand == RANDOM_SHIFT:
+            v = v + float(wl.shift[r, j])
+            if v >= 1.0:
+                v = v - 1.0
+    if wl.map == MAP_CENTER:
+        return v - 0.5
+    if wl.map == MAP_TENT:
+        return 1.0 - abs(1.0 - 2.0 * v)
+    if wl.map == MAP_INVNORM:
+        return float(ndtri(v))
+    return v
+
+
+def point_matrix(wl, r: int = 0) -> np.ndarray:
+    N = 1 << wl.m
+    return np.array([[value(wl, r, k, j) for j in range(wl.s)] for k in range(N)])

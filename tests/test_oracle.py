@@ -1,0 +1,341 @@
+"""Pins of the FP64 oracle against what the paper and mathematics fix (CPU only).
+
+Each test names the passage it follows.  None of them re-types the oracle's
+own formula: tables are checked against the unreduced definitions computed by
+brute force, the product against the dense X A, the estimate against exact
+closed forms and known integrals, the gradient against a dense matrix product
+and finite differences.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy.special import ndtri
+
+import brute
+from paper_2305_11645_amd import inputs as I
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+KINDS = [I.LATTICE, I.POLY_LATTICE, I.DIGITAL_NET]
+RANDS = [I.NO_SHIFT, I.RANDOM_SHIFT, I.DIGITAL_SHIFT]
+
+
+def small(kind, rand, mp=I.MAP_ID, m=6, s=9, t=5, R=2, seed=3, w=None, g=I.G_COS, h=I.H_ID, K=0.0, c=1.0):
+    if w is None:
+        w = I.w_log2(s, m + 1)  # includes coordinates with w_j >= m
+    return I.make_custom(kind=kind, m=m, s=s, t=t, w=w, rand=rand, R=R, map=mp, g=g, h=h, K=K, c=c,
+                         seed=seed)
+
+
+# ------------------------------------------------------------------ point tables
+
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("rand", RANDS)
+@pytest.mark.parametrize("mp", [I.MAP_ID, I.MAP_CENTER, I.MAP_TENT])
+def test_tables_match_unreduced_definition(oracle_lib, kind, rand, mp):
+    """Sec. 1.1/1.3 and eq. def:digital, reduced_genmat_net2: the reduced table
+    of coordinate j, indexed by k mod n_j, reproduces the unreduced point set
+    exactly (bit for bit in FP64) for every k (periodicity invariant)."""
+    O = oracle_lib
+    wl = small(kind, rand, mp, m=6, s=10)
+    for r in range(wl.R):
+        X = brute.point_matrix(wl, r)
+        for j in range(wl.s):
+            vals = O.point_values(wl, r, j)
+            n = len(vals)
+            assert n == 2 ** (wl.m - min(int(wl.w[j]), wl.m))
+            k = np.arange(wl.N)
+            np.testing.assert_array_equal(vals[k % n], X[:, j])
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_tables_invnorm_map(oracle_lib, kind):
+    """Sec. 2.3 map Phi^-1 on the distinct values: AS241 agrees with the
+    library quantile (scipy ndtri) to a few ulp; digitally shifted values lie
+    strictly inside (0, 1) so every value is finite."""
+    O = oracle_lib
+    wl = small(kind, I.DIGITAL_SHIFT, I.MAP_INVNORM, m=7, s=8)
+    for j in range(wl.s):
+        vals = O.point_values(wl, 0, j)
+        X = brute.point_matrix(wl, 0)[:, j]
+        n = len(vals)
+        ref = X[np.arange(wl.N) % n]
+        assert np.all(np.isfinite(vals))
+        np.testing.assert_allclose(vals[np.arange(wl.N) % n], ref, rtol=4e-15, atol=1e-300)
+
+
+def test_as241_against_library_quantile(oracle_lib):
+    """Wichura's AS241 agrees with an independent quantile routine over the
+    whole range, including the two tails handled by separate rational fits."""
+    O = oracle_lib
+    ps = np.concatenate([np.logspace(-300, -1, 400), np.linspace(0.05, 0.95, 301),
+                         1 - np.logspace(-16, -1, 200)])
+    for p in ps:
+        a, b = O.invnorm(float(p)), float(ndtri(p))
+        assert abs(a - b) <= 2e-15 * max(1.0, abs(b)), (p, a, b)
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_value_multiplicity_and_zero_columns(oracle_lib, kind):
+    """Sec. 1.3 and Sec. 3: coordinate j takes each value c / b^{m-min(w_j,m)}
+    exactly b^{min(w_j,m)} times; for j > s* (w_j >= m) every value is 0."""
+    O = oracle_lib
+    wl = small(kind, I.NO_SHIFT, m=8, s=12, w=I.w_log2(12, 9))
+    X = brute.point_matrix(wl, 0)
+    for j in range(wl.s):
+        nb = wl.m - min(int(wl.w[j]), wl.m)
+        c = np.round(X[:, j] * 2 ** nb).astype(np.int64)
+        assert np.all(c / 2 ** nb == X[:, j])
+        counts = np.bincount(c, minlength=2 ** nb)
+        assert np.all(counts == 2 ** min(int(wl.w[j]), wl.m))
+        if int(wl.w[j]) >= wl.m:
+            assert np.all(X[:, j] == 0.0)
+            assert np.all(O.point_values(wl, 0, j) == 0.0)
+
+
+def test_worked_example_golden(oracle_lib):
+    """Section 1, display "ex": N = 4 points with N_1 = 4, N_2 = 2, N_3 = 1
+    distinct values (w = (0, 1, 2)); the golden file holds the paper's listing
+    as value indices.  The reduced tables indexed by k mod n_j reproduce it."""
+    O = oracle_lib
+    rows = [list(map(int, ln.split())) for ln in open(os.path.join(GOLDEN, "worked_example.txt"))
+            if ln.strip() and not ln.startswith("#")]
+    wl = I.make_custom(kind=I.LATTICE, m=2, s=3, t=1, w=[0, 1, 2], seed=11)
+    X = brute.point_matrix(wl, 0)
+    for k, i1, i2, i3 in rows:
+        for j, idx in enumerate((i1, i2, i3)):
+            assert X[k, j] == O.point_values(wl, 0, j)[idx]
+
+
+# ------------------------------------------------------------------ product
+
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("rand", RANDS)
+def test_alg1_equals_dense(oracle_lib, kind, rand):
+    """Algorithm 1 (Theorem 2: it computes X A exactly up to rounding) agrees
+    with the plain dense product of eq. QMC_matrix built from the unreduced
+    definitions, to 1e-13 relative Frobenius."""
+    O = oracle_lib
+    for seed in range(3):
+        mp = I.MAP_INVNORM if rand == I.DIGITAL_SHIFT and seed == 2 else I.MAP_ID
+        wl = small(kind, rand, mp, m=8, s=17, t=11, R=2, seed=seed)
+        for r in range(wl.R):
+            X = O.point_matrix_unreduced(wl, r)
+            Yd = O.dense_matvec(X, wl.A.astype(np.float64))
+            Yr = O.reduced_matvec(wl, r)
+            assert np.linalg.norm(Yr - Yd) <= 1e-13 * np.linalg.norm(Yd)
+
+
+def test_alg1_c1_and_c2_sizes(oracle_lib):
+    """The same check at the full C1 size and at C2 with m reduced to 12."""
+    O = oracle_lib
+    for wl in (I.make_config(1), I.make_config(2, m=12, R=2)):
+        for r in range(wl.R):
+            X = O.point_matrix_unreduced(wl, r)
+            Yd = O.dense_matvec(X, wl.A.astype(np.float64))
+            Yr = O.reduced_matvec(wl, r)
+            assert np.linalg.norm(Yr - Yd) <= 1e-13 * np.linalg.norm(Yd)
+
+
+def test_alg1_special_cases(oracle_lib):
+    """w = 0 everywhere is the ordinary lattice: the product is a plain GEMM
+    (numpy matmul of the point matrix); A = I_s gives Y = X exactly."""
+    O = oracle_lib
+    wl = I.make_custom(kind=I.LATTICE, m=7, s=6, t=6, w=[0] * 6, rand=I.RANDOM_SHIFT, R=1, seed=5)
+    X = O.point_matrix_unreduced(wl, 0)
+    Y = O.reduced_matvec(wl, 0)
+    np.testing.assert_allclose(Y, X @ wl.A.astype(np.float64), rtol=1e-13, atol=1e-13)
+    eye = np.eye(6)
+    for kind in KINDS:
+        wl = small(kind, I.RANDOM_SHIFT, m=7, s=6, t=6, R=1)
+        X = O.point_matrix_unreduced(wl, 0)
+        Y = O.reduced_matvec(wl, 0, A=eye)
+        np.testing.assert_array_equal(Y, X)
+
+
+def test_alg1_operation_count(oracle_lib):
+    """Theorem 2: the multiply-adds of Algorithm 1 number t * sum_{j <= s*} n_j."""
+    O = oracle_lib
+    for c in (1, 2):
+        wl = I.make_config(c) if c == 1 else I.make_config(2, m=12, R=1)
+        wl.rand, wl.shift = I.NO_SHIFT, None
+        P, cnt = O.alg1(wl, 0)
+        nj = [2 ** (wl.m - int(w)) for w in wl.w if int(w) < wl.m]
+        assert cnt == wl.t * sum(nj)
+
+
+# ------------------------------------------------------------------ estimate
+
+def _mu(wl, r, j):
+    """Mean of coordinate j over the N points, closed form (see the test below)."""
+    nb = wl.m - min(int(wl.w[j]), wl.m)
+    n = 2 ** nb
+    if wl.rand == I.RANDOM_SHIFT:
+        d = float(wl.shift[r, j])
+        return (n - 1 + 2 * ((n * d) % 1.0)) / (2 * n)
+    if wl.rand == I.DIGITAL_SHIFT:
+        dl = int(wl.dshift[r, j]) & ((1 << (52 - nb)) - 1)
+        return (n - 1) / (2 * n) + dl / 2 ** 52 + 2 ** -53
+    return (n - 1) / (2 * n)
+
+
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("rand", RANDS)
+def test_linear_integrand_exact(oracle_lib, kind, rand):
+    """eq. QMC-rule with g(y) = y, h(u) = u: Q = t^-1 sum_i sum_j a_ji mu_j,
+    where mu_j is the mean of the values c/n_j (each taken b^{w_j} times,
+    Sec. 1.3), shifted: unshifted (n-1)/(2n); random shift (Sec. 1.2)
+    (n-1+2{n Delta})/(2n); digital shift (n-1)/(2n) + delta_lo 2^-52 + 2^-53.
+    Holds exactly at any N, so it pins tables, product and mean together."""
+    O = oracle_lib
+    for mp, off in ((I.MAP_ID, 0.0), (I.MAP_CENTER, -0.5)):
+        wl = small(kind, rand, mp, m=10, s=40, t=7, R=3, g=I.G_ID, h=I.H_ID)
+        Q, _ = O.estimate(wl)
+        A = wl.A.astype(np.float64)
+        for r in range(wl.R):
+            mu = np.array([_mu(wl, r, j) + off for j in range(wl.s)])
+            ref = float(np.mean(mu @ A))
+            assert abs(Q[r] - ref) <= 1e-13 * max(1.0, abs(ref))
+
+
+def test_neumaier():
+    """Compensated summation recovers sums that plain summation loses."""
+    from oracle import oracle as O
+    assert O.neumaier(np.array([1.0, 1e100, 1.0, -1e100])) == 2.0
+    x = np.full(10 ** 5, 0.1)
+    assert abs(O.neumaier(x) - 1e4) < 1e-10
+
+
+def _cos_closed_form(A):
+    """Sec. 1 integral over U[0,1)^s of t^-1 sum_i cos(x^T a_i):
+    t^-1 sum_i Re prod_j (e^{i a_ji} - 1)/(i a_ji)."""
+    phi = np.where(A == 0, 1.0 + 0j, (np.exp(1j * A) - 1) / (1j * np.where(A == 0, 1.0, A)))
+    return float(np.mean(np.real(np.prod(phi, axis=0))))
+
+
+def test_cos_mean_converges_c2(oracle_lib):
+    """C2 (randomly shifted, Sec. 1.2): the mean over the 8 shifts lies within
+    4 standard errors of the closed-form integral."""
+    O = oracle_lib
+    wl = I.make_config(2)
+    Q, _ = O.estimate(wl)
+    Iex = _cos_closed_form(wl.A.astype(np.float64))
+    se = Q.std(ddof=1) / math.sqrt(len(Q))
+    assert abs(Q.mean() - Iex) <= 4 * se
+    assert se < 1e-3
+
+
+def test_exp_mean_converges_kl(oracle_lib):
+    """C4 recipe at reduced size: points mapped to [-1/2, 1/2)^s, g = exp(-y):
+    the integral is t^-1 sum_i prod_j sinh(a_ji/2)/(a_ji/2)."""
+    O = oracle_lib
+    wl = I.make_config(4, m=12, s=256, t=64, R=8)
+    Q, _ = O.estimate(wl)
+    A = wl.A.astype(np.float64)
+    half = A / 2
+    fac = np.where(half == 0, 1.0, np.sinh(half) / np.where(half == 0, 1.0, half))
+    Iex = float(np.mean(np.prod(fac, axis=0)))
+    se = Q.std(ddof=1) / math.sqrt(len(Q))
+    assert abs(Q.mean() - Iex) <= 4 * se
+    assert se < 1e-4 * Iex
+
+
+def test_gaussian_expectation_converges(oracle_lib):
+    """Sec. 1, Gaussian setting: with y = A^T Phi^-1(x), A = L^T, E exp(0.2 y_i)
+    = exp(0.02 Sigma_ii) (Sigma = A^T A).  C3 recipe at reduced size, h = id,
+    digitally shifted net, 8 shifts."""
+    O = oracle_lib
+    wl = I.make_config(3, m=12, s=64, t=64, R=8)
+    wl.h = I.H_ID
+    Q, _ = O.estimate(wl)
+    A = wl.A.astype(np.float64)
+    Iex = float(np.mean(np.exp(0.02 * np.sum(A * A, axis=0))))
+    se = Q.std(ddof=1) / math.sqrt(len(Q))
+    assert abs(Q.mean() - Iex) <= 4 * se
+    assert abs(Iex - math.exp(0.02)) < 1e-6
+
+
+def test_exponential_kernel_cholesky_closed_form():
+    """C3 input: the Cholesky factor of exp(-|u-v|/0.1) on a uniform grid has the
+    closed form L_ij = exp(-(u_i - u_j)/0.1) sigma_j (i >= j), sigma_0 = 1,
+    sigma_j = sqrt(1 - exp(-2 (u_j - u_{j-1}) / 0.1))."""
+    n = 256
+    L = I.exp_kernel_cholesky_T(n).T
+    u = (np.arange(n) + 0.5) / n
+    sig = np.ones(n)
+    sig[1:] = np.sqrt(1 - np.exp(-2 * np.diff(u) / 0.1))
+    ref = np.tril(np.exp(-(u[:, None] - u[None, :]) / 0.1) * sig[None, :])
+    np.testing.assert_allclose(L, ref, rtol=0, atol=1e-12)
+
+
+# ------------------------------------------------------------------ gradient
+
+def _dense_grad(wl, A, X, r):
+    """dQ/dA = X^T G, G_ki = N^-1 h'(u_k) t^-1 g'(y_ki), with numpy matmuls."""
+    Y = X @ A
+    N, t = Y.shape
+    if wl.g == I.G_COS:
+        gv, gd = np.cos(Y), -np.sin(Y)
+    elif wl.g == I.G_EXP:
+        gv, gd = np.exp(wl.c * Y), wl.c * np.exp(wl.c * Y)
+    else:
+        gv, gd = Y, np.ones_like(Y)
+    u = gv.mean(axis=1)
+    hd = (u > wl.K).astype(float) if wl.h == I.H_CALL else np.ones_like(u)
+    G = hd[:, None] * gd / (N * t)
+    return X.T @ G
+
+
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("g,h", [(I.G_COS, I.H_ID), (I.G_EXP, I.H_CALL), (I.G_ID, I.H_ID)])
+def test_gradient_equals_dense(oracle_lib, kind, g, h):
+    """The fold form of dQ/dA (residue-class sums, transpose of Algorithm 1)
+    equals the dense X^T G built from the unreduced point matrix."""
+    O = oracle_lib
+    rand = I.DIGITAL_SHIFT if kind == I.DIGITAL_NET else I.RANDOM_SHIFT
+    wl = small(kind, rand, m=8, s=13, t=6, R=2, g=g, h=h, K=1.0, c=0.3)
+    Q, dA = O.estimate_grad(wl)
+    A = wl.A.astype(np.float64)
+    for r in range(wl.R):
+        X = O.point_matrix_unreduced(wl, r)
+        ref = _dense_grad(wl, A, X, r)
+        assert np.linalg.norm(dA[r] - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+def test_gradient_finite_differences(oracle_lib):
+    """Central differences of the oracle estimate along a random direction V
+    agree with <dA, V> (C5 recipe at reduced size)."""
+    O = oracle_lib
+    wl = I.make_config(5, m=9, s=32, t=16, R=1)
+    A = wl.A.astype(np.float64)
+    _, dA = O.estimate_grad(wl, A=A)
+    V = np.random.default_rng(1).standard_normal(A.shape)
+    eps = 1e-5
+    qp, _ = O.estimate(wl, A=A + eps * V)
+    qm, _ = O.estimate(wl, A=A - eps * V)
+    fd = (qp[0] - qm[0]) / (2 * eps)
+    an = float(np.sum(dA[0] * V))
+    assert abs(fd - an) <= 1e-8 * max(1.0, abs(an))
+
+
+def test_gradient_matches_closed_form_derivative(oracle_lib):
+    """For g = cos on U[0,1)^s the exact integral is t^-1 sum_i Re prod_j
+    phi(a_ji), phi(a) = (e^{ia}-1)/(ia); its derivative is t^-1 Re phi'(a_ji)
+    prod_{l != j} phi(a_li).  The randomly shifted QMC gradient (mean of 8
+    shifts) approaches it."""
+    O = oracle_lib
+    wl = I.make_config(5, m=14, s=64, t=8, R=8)
+    A = wl.A.astype(np.float64)
+    _, dA = O.estimate_grad(wl, A=A)
+    safe = np.where(A == 0, 1.0, A)
+    phi = (np.exp(1j * safe) - 1) / (1j * safe)
+    dphi = (np.exp(1j * safe) * (1j * safe) * 1j - (np.exp(1j * safe) - 1) * 1j) / (1j * safe) ** 2
+    prod = np.prod(phi, axis=0)
+    ref = np.real(dphi * prod[None, :] / phi) / A.shape[1]
+    est = dA.mean(axis=0)
+    se = dA.std(axis=0, ddof=1) / math.sqrt(dA.shape[0])
+    # Frobenius error within 4 standard errors of the shift average, and small
+    assert np.linalg.norm(est - ref) <= 4 * np.sqrt(np.sum(se ** 2))
+    assert np.linalg.norm(est - ref) <= 1e-2 * np.linalg.norm(ref)
