@@ -1,0 +1,200 @@
+#!/usr/bin/env python3
+"""Benchmark: reduced QMC estimate on one MI355X.
+
+One step = qmc_estimate over every randomisation of the workload (point tables,
+grouped upper-level products on the matrix cores, fused leaf pass with g and
+the FP64 mean).  Inputs are resident in HBM before timing starts.
+
+Prints ONE JSON line:
+  metric/value   effective GFLOP/s = 2 N s t R / time (dense-equivalent count)
+  roofline       the dominant kernel (the fused leaf pass) against the VALU peak
+  cpu_baseline   the FP64 oracle on the host cores
+  dense          the plain form on the same GPU: point matrix + FP32 GEMM + f + mean
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+# MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz = 3.93e13 VALU lane-slots/s.
+# One FP32 FMA per slot = 2 flops -> 78.6 TFLOP/s without packed FP32 (which
+# this build does not emit); transcendentals (v_cos, v_exp) take 4 slots.
+VALU_SLOTS_PER_S = 256 * 64 * 2.4e9
+VALU_PEAK_TFLOPS = 2 * VALU_SLOTS_PER_S / 1e12
+G_SLOTS = {0: 0, 1: 5, 2: 5}  # per evaluation of g: id; cos = mul + v_cos; exp = mul + v_exp
+
+
+def leaf_algorithmic_slots(wl, split: int) -> float:
+    """VALU lane operations the fused leaf pass must perform per launch (all shifts):
+    the lower-level multiply-adds t R sum_{j: min(w_j,m) < L'} n_j (Theorem 2's
+    count on those coordinates), one add per subtree root and upper level, and
+    per point and column one g and one accumulation."""
+    m, t, R, N = wl.m, wl.t, wl.R, wl.N
+    lev = np.minimum(wl.w, m)
+    nlow = sum(2 ** (m - int(I)) for I in lev if I < split)
+    nup = len({int(I) for I in lev if I >= split})
+    nsub = 2 ** (m - split)
+    return float(t * R * nlow + t * R * nsub * nup + N * t * R * (1 + G_SLOTS[wl.g]))
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--config", type=int, default=2, help="workload C1..C5 (default C2)")
+    ap.add_argument("--prec", type=int, default=None, help="0 = FP32, 1 = split-BF16x3")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-dense", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the sharding plan is described in DESIGN.md)", file=sys.stderr)
+        return 2
+
+    import torch
+
+    import paper_2305_11645_amd as q
+    from paper_2305_11645_amd import inputs as I
+
+    torch.cuda.set_device(0)
+    wl = I.make_config(args.config)
+    prec = wl.prec if args.prec is None else args.prec
+    f = q.Integrand_.of(wl)
+    pts = q.Points.from_workload(wl)
+    A = torch.from_numpy(wl.A).cuda()
+    ws = pts.workspace(1, wl.t, f, prec)
+    Q = torch.empty(wl.R, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def step():
+        q.estimate(pts, A, f, prec, Q=Q, workspace=ws)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    Qg = Q.cpu().numpy()
+
+    # per-kernel durations: the same steps again with the library's event hooks
+    q.timing.reset()
+    q.timing.enable(True)
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    q.timing.enable(False)
+    kern = {}
+    for name in ("tables", "levels", "leaf", "reduce"):
+        tot, n = q.timing.read(name)
+        if n:
+            kern[name] = {"avg_ms": tot / n, "launches": n}
+    q.timing.reset()
+
+    flops = 2.0 * wl.N * wl.s * wl.t * wl.R
+    value = flops / (ms * 1e-3) / 1e9
+    leaf_ms = kern.get("leaf", {}).get("avg_ms", float("nan"))
+    slots = leaf_algorithmic_slots(wl, pts.split_level)
+    achieved = 2 * slots / (leaf_ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "kernel": "leaf_kernel", "achieved": round(achieved, 3),
+                "peak": round(VALU_PEAK_TFLOPS, 1), "unit": "TFLOP/s",
+                "frac": round(achieved / VALU_PEAK_TFLOPS, 4), "traffic": None,
+                "avg_ms": round(leaf_ms, 5), "algorithmic_lane_ops": slots}
+
+    # accuracy gate and CPU baseline: the FP64 oracle
+    rel_err = None
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        sample_R = wl.R
+        budget = 25.0
+        t0 = time.perf_counter()
+        Qo, _ = O.estimate(wl, shifts=1)
+        one = time.perf_counter() - t0
+        if one * wl.R > budget:
+            sample_R = max(1, int(budget // max(one, 1e-9)))
+        t0 = time.perf_counter()
+        Qo, _ = O.estimate(wl, shifts=sample_R)
+        dt = time.perf_counter() - t0
+        rel_err = float(np.max(np.abs(Qg[:sample_R] - Qo) / np.abs(Qo)))
+        cpu_flops = 2.0 * wl.N * wl.s * wl.t * sample_R
+        cpu = {"value": round(cpu_flops / dt / 1e9, 3), "unit": "GFLOP/s", "cores": O.num_threads(),
+               "kind": "oracle", "seconds": round(dt, 3),
+               "sample": f"{sample_R} of {wl.R} randomisations of the full workload, FP64 Algorithm 1 "
+                         f"with point tables, f and compensated mean"}
+
+    dense = None
+    if not args.no_dense:
+        X = torch.empty((wl.R * wl.N, wl.s), dtype=torch.float32, device="cuda")
+
+        def dense_step():
+            for r in range(wl.R):
+                X[r * wl.N:(r + 1) * wl.N].copy_(q.point_matrix(pts, r))
+            Y = X @ A
+            if wl.g == I.G_COS:
+                gY = torch.cos(Y)
+            elif wl.g == I.G_EXP:
+                gY = torch.exp(wl.c * Y)
+            else:
+                gY = Y
+            u = gY.double().mean(dim=1).view(wl.R, wl.N)
+            if wl.h == I.H_CALL:
+                u = torch.clamp(u - wl.K, min=0.0)
+            return u.mean(dim=1)
+
+        dense_step()
+        torch.cuda.synchronize()
+        d0, d1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        nd = max(3, min(args.steps, 10))
+        d0.record(stream)
+        for _ in range(nd):
+            Qd = dense_step()
+        d1.record(stream)
+        torch.cuda.synchronize()
+        dms = d0.elapsed_time(d1) / nd
+        dense = {"ms_per_step": round(dms, 4), "value": round(flops / (dms * 1e-3) / 1e9, 1),
+                 "speedup_reduced_vs_dense": round(dms / ms, 2),
+                 "rel_diff_vs_reduced": float(np.max(np.abs(Qd.cpu().numpy() - Qg) / np.abs(Qg)))}
+        del X
+
+    out = {
+        "metric": "effective GFLOP/s (2*N*s*t*R/time), reduced QMC estimate vs dense X*A, rel err <= 1e-6",
+        "value": round(value, 1),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec == I.FP32 else "bf16x3",
+        "data": "synthetic (seeded generators and shifts, random-normal A)",
+        "config": {"workload": wl.name, "N": wl.N, "s": wl.s, "t": wl.t, "R": wl.R,
+                   "split_level": pts.split_level, "distinct_values_per_shift": pts.distinct_values},
+        "rel_err_vs_oracle": rel_err,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "dense": dense,
+        "kernels": kern,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

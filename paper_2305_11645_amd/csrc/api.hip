@@ -1,0 +1,565 @@
+// C ABI of libqmcred: validation, level planning, workspace and launch order.
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <utility>
+#include <vector>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+
+#include "qmc_internal.h"
+
+struct qmc_points_s {
+  int device = 0;
+  qmc::Geometry G{};
+  qmc::DevSpec D{};
+  void *d_gen = nullptr, *d_nb = nullptr, *d_shift = nullptr, *d_dshift = nullptr;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+qmc_status fail(qmc_status s, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return s;
+}
+
+qmc_status hip_fail(hipError_t e, const char *what) {
+  return fail(QMC_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define QMC_HIP(call, what)                                  \
+  do {                                                       \
+    hipError_t e_ = (call);                                  \
+    if (e_ != hipSuccess) return hip_fail(e_, what);         \
+  } while (0)
+
+// ------------------------------------------------------------ timing registry
+std::mutex g_tm_mu;
+bool g_tm_on = false;
+std::unordered_map<std::string, std::vector<std::pair<hipEvent_t, hipEvent_t>>> g_tm;
+
+// Restores the caller's device on scope exit.
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
+    else prev = -1;
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+bool is_prime(int b) {
+  if (b < 2) return false;
+  for (int d = 2; d * d <= b; ++d)
+    if (b % d == 0) return false;
+  return true;
+}
+
+// Split level L' and record/table layout (see qmc_internal.h).
+void plan_geometry(qmc::Geometry &G, const int32_t *w) {
+  using namespace qmc;
+  const int m = G.m;
+  for (int I = 0; I <= m; ++I) {
+    G.lev[I] = Level{};
+    G.lev[I].nb = m - I;
+    G.lev[I].j0 = -1;
+  }
+  for (int j = 0; j < G.s; ++j) {
+    const int I = w[j] < m ? w[j] : m;
+    if (G.lev[I].j0 < 0) G.lev[I].j0 = j;
+    G.lev[I].tau++;
+  }
+  int jcur = 0;
+  for (int I = 0; I <= m; ++I) {  // empty levels get the j0 of the next block
+    if (G.lev[I].j0 < 0) G.lev[I].j0 = jcur;
+    jcur = G.lev[I].j0 + G.lev[I].tau;
+  }
+  int split = m < kMaxSplit ? m : kMaxSplit;
+  if (const char *env = getenv("QMC_SPLIT_LEVEL")) {
+    const int v = atoi(env);
+    if (v >= 0 && v <= split) split = v;
+  }
+  while (split > 0) {
+    int jl = 0;
+    for (int I = 0; I < split; ++I) jl += G.lev[I].tau;
+    if (jl <= kMaxLowRows) break;
+    --split;
+  }
+  G.split = split;
+  G.jlow = 0;
+  for (int I = 0; I < split; ++I) G.jlow += G.lev[I].tau;
+  G.N = int64_t(1) << m;
+  G.nsub = int64_t(1) << (m - split);
+  int64_t off = 0;
+  for (int I = split - 1; I >= 0; --I) {
+    G.lev[I].off = off;
+    off += (int64_t)G.lev[I].tau << (split - I);
+  }
+  G.rec = off;
+  G.lower_total = G.nsub * G.rec;
+  G.nup = 0;
+  int64_t toff = 0, uoff = 0;
+  for (int I = split; I <= m; ++I) {
+    if (G.lev[I].tau == 0) continue;
+    G.up[G.nup++] = I;
+    G.lev[I].off = toff;
+    G.lev[I].uoff = uoff;
+    toff += (int64_t(1) << G.lev[I].nb) * G.lev[I].tau;
+    uoff += int64_t(1) << G.lev[I].nb;
+  }
+  G.table_total = G.lower_total + toff;
+  G.urows = uoff;
+}
+
+// ------------------------------------------------------------ workspace
+struct Carve {
+  char *base;
+  size_t used = 0;
+  template <class T>
+  T *take(size_t count) {
+    T *p = base ? reinterpret_cast<T *>(base + used) : nullptr;
+    used += qmc::round_up((int64_t)(count * sizeof(T)), 256);
+    return p;
+  }
+};
+
+enum Op { kOpMatvec = 0, kOpEstimate = 1, kOpGrad = 2 };
+
+struct Work {
+  float *tables, *U, *ppart, *S, *dlow, *dup, *hd;
+  double *partial, *ppartial;
+};
+
+size_t carve(const qmc::Geometry &G, int op, int t, const qmc_integrand *f, int nr, char *base,
+             Work &wk) {
+  using namespace qmc;
+  Carve c{base};
+  const int64_t ldu = round_up(t, kTileT);
+  const int64_t tct = ceil_div(t, kTileT);
+  const LeafPlan lp = leaf_plan(G, t, nr, kModeSum);
+  const LeafPlan lg = leaf_plan(G, t, nr, kModeGrad);
+  wk = Work{};
+  wk.tables = c.take<float>((size_t)nr * G.table_total);
+  wk.U = c.take<float>((size_t)nr * G.urows * ldu);
+  if (op == kOpMatvec) return c.used;
+  const bool sep = f->h == QMC_H_ID;
+  wk.partial = c.take<double>((size_t)nr * (lp.gx > lg.gx ? lp.gx : lg.gx) * tct);
+  if (!sep) {
+    wk.ppart = c.take<float>((size_t)nr * tct * G.N);
+    wk.ppartial = c.take<double>((size_t)nr * point_h_blocks(G));
+  }
+  if (op == kOpGrad) {
+    wk.S = c.take<float>((size_t)nr * 2 * G.nsub * ldu);
+    wk.dlow = c.take<float>((size_t)nr * lg.gx * tct * (G.jlow > 0 ? G.jlow : 1) * kTileT);
+    wk.dup = c.take<float>((size_t)nr * (levels_adj_part_floats(G, t, ldu) + 1));
+    if (!sep) wk.hd = c.take<float>((size_t)nr * G.N);
+  }
+  return c.used;
+}
+
+// Stream-ordered workspace owned by one call when the caller passes none.
+struct CallWorkspace {
+  void *ptr = nullptr;
+  hipStream_t st = nullptr;
+  ~CallWorkspace() {
+    if (ptr) (void)hipFreeAsync(ptr, st);
+  }
+};
+
+qmc_status check_points(qmc_points p) {
+  if (!p) return fail(QMC_EINVAL, "null point set");
+  return QMC_OK;
+}
+
+qmc_status check_matrix(const float *A, int32_t t, int64_t lda, int32_t prec) {
+  if (!A) return fail(QMC_EINVAL, "A is null");
+  if (t < 1) return fail(QMC_EINVAL, "t = %d must be >= 1", t);
+  if (t > (1 << 24)) return fail(QMC_EUNSUPPORTED, "t = %d exceeds 2^24", t);
+  if (lda < t) return fail(QMC_EINVAL, "lda = %lld < t = %d", (long long)lda, t);
+  if (prec != QMC_FP32 && prec != QMC_SPLIT_BF16X3)
+    return fail(QMC_EINVAL, "unknown precision %d", prec);
+  return QMC_OK;
+}
+
+qmc_status check_integrand(const qmc_integrand *f) {
+  if (!f) return fail(QMC_EINVAL, "integrand is null");
+  if (f->g < QMC_G_ID || f->g > QMC_G_EXP) return fail(QMC_EINVAL, "unknown g %d", f->g);
+  if (f->h < QMC_H_ID || f->h > QMC_H_CALL) return fail(QMC_EINVAL, "unknown h %d", f->h);
+  return QMC_OK;
+}
+
+qmc_status get_workspace(qmc_points p, size_t need, void *ws, size_t ws_bytes, hipStream_t st,
+                         CallWorkspace &own, char *&base) {
+  (void)p;
+  if (ws) {
+    if (ws_bytes < need)
+      return fail(QMC_ENOMEM, "workspace of %zu bytes is smaller than the %zu required", ws_bytes, need);
+    if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return fail(QMC_EINVAL, "workspace not 256-byte aligned");
+    base = static_cast<char *>(ws);
+    return QMC_OK;
+  }
+  if (getenv("QMC_FAULT_INJECT") && strcmp(getenv("QMC_FAULT_INJECT"), "alloc") == 0)
+    return fail(QMC_ENOMEM, "workspace allocation failed (fault injection)");
+  hipError_t e = hipMallocAsync(&own.ptr, need > 0 ? need : 256, st);
+  if (e != hipSuccess) {
+    own.ptr = nullptr;
+    return fail(QMC_ENOMEM, "workspace allocation of %zu bytes failed: %s", need, hipGetErrorString(e));
+  }
+  own.st = st;
+  base = static_cast<char *>(own.ptr);
+  return QMC_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ timing hook
+namespace qmc {
+LaunchTimer::LaunchTimer(const char *n, hipStream_t s) : name(n), st(s) {
+  if (!g_tm_on) return;
+  hipEvent_t e;
+  if (hipEventCreate(&e) == hipSuccess && hipEventRecord(e, st) == hipSuccess) ev0 = e;
+}
+LaunchTimer::~LaunchTimer() {
+  if (!ev0) return;
+  hipEvent_t e1;
+  if (hipEventCreate(&e1) != hipSuccess) return;
+  if (hipEventRecord(e1, st) != hipSuccess) return;
+  std::lock_guard<std::mutex> lk(g_tm_mu);
+  g_tm[name].emplace_back((hipEvent_t)ev0, e1);
+}
+}  // namespace qmc
+
+extern "C" {
+
+const char *qmc_status_string(qmc_status s) {
+  switch (s) {
+    case QMC_OK: return "success";
+    case QMC_EINVAL: return "invalid argument";
+    case QMC_EUNSUPPORTED: return "unsupported";
+    case QMC_ENOMEM: return "out of memory";
+    case QMC_EDEVICE: return "device error";
+  }
+  return "unknown status";
+}
+
+const char *qmc_last_error(void) { return g_last_error.c_str(); }
+
+qmc_status qmc_timing_enable(int32_t on) {
+  g_tm_on = on != 0;
+  return QMC_OK;
+}
+
+qmc_status qmc_timing_reset(void) {
+  std::lock_guard<std::mutex> lk(g_tm_mu);
+  for (auto &kv : g_tm)
+    for (auto &pr : kv.second) {
+      (void)hipEventSynchronize(pr.second);
+      (void)hipEventDestroy(pr.first);
+      (void)hipEventDestroy(pr.second);
+    }
+  g_tm.clear();
+  return QMC_OK;
+}
+
+qmc_status qmc_timing_read(const char *name, double *ms, int64_t *launches) {
+  if (!name || !ms || !launches) return fail(QMC_EINVAL, "null argument");
+  std::lock_guard<std::mutex> lk(g_tm_mu);
+  *ms = 0.0;
+  *launches = 0;
+  auto it = g_tm.find(name);
+  if (it == g_tm.end()) return QMC_OK;
+  for (auto &pr : it->second) {
+    QMC_HIP(hipEventSynchronize(pr.second), "hipEventSynchronize");
+    float x = 0.f;
+    QMC_HIP(hipEventElapsedTime(&x, pr.first, pr.second), "hipEventElapsedTime");
+    *ms += x;
+    ++*launches;
+  }
+  return QMC_OK;
+}
+
+qmc_status qmc_points_init(qmc_points *out, const qmc_point_spec *sp) {
+  using namespace qmc;
+  if (!out) return fail(QMC_EINVAL, "out is null");
+  *out = nullptr;
+  if (!sp) return fail(QMC_EINVAL, "spec is null");
+  if (!is_prime(sp->b)) return fail(QMC_EINVAL, "b = %d is not prime", sp->b);
+  if (sp->b != 2) return fail(QMC_EUNSUPPORTED, "only b = 2 is supported (b = %d)", sp->b);
+  if (sp->m < 1 || sp->m > kMaxM) return fail(QMC_EUNSUPPORTED, "m = %d outside [1, %d]", sp->m, kMaxM);
+  if (sp->s < 1) return fail(QMC_EINVAL, "s = %d must be >= 1", sp->s);
+  if (sp->kind < QMC_LATTICE || sp->kind > QMC_DIGITAL_NET) return fail(QMC_EINVAL, "unknown kind %d", sp->kind);
+  if (!sp->w || !sp->gen) return fail(QMC_EINVAL, "w or gen is null");
+  const int m = sp->m, s = sp->s;
+  if (sp->w[0] != 0) return fail(QMC_EINVAL, "w[0] = %d must be 0", sp->w[0]);
+  for (int j = 1; j < s; ++j) {
+    if (sp->w[j] < sp->w[j - 1]) return fail(QMC_EINVAL, "w decreases at j = %d", j);
+  }
+  std::vector<uint32_t> gen;
+  std::vector<int32_t> nbv(s);
+  for (int j = 0; j < s; ++j) nbv[j] = m - (sp->w[j] < m ? sp->w[j] : m);
+  if (sp->kind == QMC_DIGITAL_NET) {
+    gen.resize((size_t)s * m);
+    for (int j = 0; j < s; ++j) {
+      const uint64_t mask = (uint64_t(1) << nbv[j]) - 1;
+      for (int q = 0; q < m; ++q) {
+        const uint64_t wd = sp->gen[(size_t)j * m + q];
+        if (wd >> m) return fail(QMC_EINVAL, "net column word (j=%d, q=%d) has bits beyond row m", j, q + 1);
+        if (q >= nbv[j] && (wd & mask))
+          return fail(QMC_EUNSUPPORTED,
+                      "reduced net is not periodic: column %d of coordinate %d is nonzero in its first %d rows",
+                      q + 1, j, nbv[j]);
+        gen[(size_t)j * m + q] = (uint32_t)wd;
+      }
+    }
+  } else {
+    gen.resize(s);
+    for (int j = 0; j < s; ++j) {
+      const uint64_t z = sp->gen[j];
+      if (nbv[j] == 0) {
+        if (z != 1) return fail(QMC_EINVAL, "generator of coordinate %d must be 1 (w_j >= m)", j);
+      } else if ((z & 1u) == 0 || z >= (uint64_t(1) << nbv[j])) {
+        return fail(QMC_EINVAL, "generator %llu of coordinate %d is not a unit below 2^%d",
+                    (unsigned long long)z, j, nbv[j]);
+      }
+      gen[j] = (uint32_t)z;
+    }
+  }
+  if (sp->rand < QMC_NO_SHIFT || sp->rand > QMC_DIGITAL_SHIFT) return fail(QMC_EINVAL, "unknown randomisation %d", sp->rand);
+  if (sp->R < 1) return fail(QMC_EINVAL, "R = %d must be >= 1", sp->R);
+  if (sp->rand == QMC_NO_SHIFT && sp->R != 1) return fail(QMC_EINVAL, "R must be 1 without a shift");
+  if (sp->R > 65535) return fail(QMC_EUNSUPPORTED, "R = %d exceeds 65535", sp->R);
+  if (sp->rand == QMC_RANDOM_SHIFT) {
+    if (!sp->shift) return fail(QMC_EINVAL, "shift is null");
+    for (int64_t i = 0; i < (int64_t)sp->R * s; ++i)
+      if (!(sp->shift[i] >= 0.0 && sp->shift[i] < 1.0)) return fail(QMC_EINVAL, "shift[%lld] outside [0,1)", (long long)i);
+  }
+  if (sp->rand == QMC_DIGITAL_SHIFT) {
+    if (!sp->dshift) return fail(QMC_EINVAL, "dshift is null");
+    for (int64_t i = 0; i < (int64_t)sp->R * s; ++i)
+      if (sp->dshift[i] >> 52) return fail(QMC_EINVAL, "dshift[%lld] >= 2^52", (long long)i);
+  }
+  if (sp->map < QMC_MAP_ID || sp->map > QMC_MAP_TENT) return fail(QMC_EINVAL, "unknown map %d", sp->map);
+  if (sp->map == QMC_MAP_INVNORM && sp->rand == QMC_NO_SHIFT)
+    return fail(QMC_EINVAL, "the inverse-normal map needs a shift (x_0 = 0)");
+
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(QMC_EDEVICE, "no HIP device");
+
+  qmc_points p = new qmc_points_s();
+  QMC_HIP(hipGetDevice(&p->device), "hipGetDevice");
+  qmc::Geometry &G = p->G;
+  G.m = m;
+  G.s = s;
+  G.kind = sp->kind;
+  G.rand = sp->rand;
+  G.map = sp->map;
+  G.R = sp->R;
+  plan_geometry(G, sp->w);
+
+  auto cleanup = [&](qmc_status st) {
+    qmc_points_free(p);
+    return st;
+  };
+  hipError_t e;
+  if ((e = hipMalloc(&p->d_gen, gen.size() * 4)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc"));
+  if ((e = hipMemcpy(p->d_gen, gen.data(), gen.size() * 4, hipMemcpyHostToDevice)) != hipSuccess)
+    return cleanup(hip_fail(e, "hipMemcpy"));
+  if ((e = hipMalloc(&p->d_nb, (size_t)s * 4)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc"));
+  if ((e = hipMemcpy(p->d_nb, nbv.data(), (size_t)s * 4, hipMemcpyHostToDevice)) != hipSuccess)
+    return cleanup(hip_fail(e, "hipMemcpy"));
+  const size_t nshift = (size_t)sp->R * s;
+  if (sp->rand == QMC_RANDOM_SHIFT) {
+    if ((e = hipMalloc(&p->d_shift, nshift * 8)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc"));
+    if ((e = hipMemcpy(p->d_shift, sp->shift, nshift * 8, hipMemcpyHostToDevice)) != hipSuccess)
+      return cleanup(hip_fail(e, "hipMemcpy"));
+  }
+  if (sp->rand == QMC_DIGITAL_SHIFT) {
+    if ((e = hipMalloc(&p->d_dshift, nshift * 8)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc"));
+    if ((e = hipMemcpy(p->d_dshift, sp->dshift, nshift * 8, hipMemcpyHostToDevice)) != hipSuccess)
+      return cleanup(hip_fail(e, "hipMemcpy"));
+  }
+  p->D.gen = static_cast<const uint32_t *>(p->d_gen);
+  p->D.nbj = static_cast<const int32_t *>(p->d_nb);
+  p->D.shift = static_cast<const double *>(p->d_shift);
+  p->D.dshift = static_cast<const uint64_t *>(p->d_dshift);
+  *out = p;
+  return QMC_OK;
+}
+
+qmc_status qmc_points_free(qmc_points p) {
+  if (!p) return QMC_OK;
+  DeviceGuard dg(p->device);
+  if (p->d_gen) (void)hipFree(p->d_gen);
+  if (p->d_nb) (void)hipFree(p->d_nb);
+  if (p->d_shift) (void)hipFree(p->d_shift);
+  if (p->d_dshift) (void)hipFree(p->d_dshift);
+  delete p;
+  return QMC_OK;
+}
+
+qmc_status qmc_points_info(qmc_points p, int64_t *N, int32_t *s, int32_t *R, int32_t *split_level,
+                           int64_t *distinct_values) {
+  if (qmc_status st = check_points(p)) return st;
+  if (N) *N = p->G.N;
+  if (s) *s = p->G.s;
+  if (R) *R = p->G.R;
+  if (split_level) *split_level = p->G.split;
+  if (distinct_values) *distinct_values = p->G.table_total;
+  return QMC_OK;
+}
+
+qmc_status qmc_point_values(qmc_points p, int32_t r, int32_t j, double *out, void *stream) {
+  if (qmc_status st = check_points(p)) return st;
+  if (r < 0 || r >= p->G.R) return fail(QMC_EINVAL, "r = %d outside [0, %d)", r, p->G.R);
+  if (j < 0 || j >= p->G.s) return fail(QMC_EINVAL, "j = %d outside [0, %d)", j, p->G.s);
+  if (!out) return fail(QMC_EINVAL, "out is null");
+  DeviceGuard dg(p->device);
+  QMC_HIP(qmc::launch_point_values(p->G, p->D, r, j, out, (hipStream_t)stream), "point values launch");
+  return QMC_OK;
+}
+
+qmc_status qmc_point_matrix(qmc_points p, int32_t r, float *X, int64_t ldx, void *stream) {
+  if (qmc_status st = check_points(p)) return st;
+  if (r < 0 || r >= p->G.R) return fail(QMC_EINVAL, "r = %d outside [0, %d)", r, p->G.R);
+  if (!X) return fail(QMC_EINVAL, "X is null");
+  if (ldx < p->G.s) return fail(QMC_EINVAL, "ldx = %lld < s = %d", (long long)ldx, p->G.s);
+  DeviceGuard dg(p->device);
+  QMC_HIP(qmc::launch_point_matrix(p->G, p->D, r, X, ldx, (hipStream_t)stream), "point matrix launch");
+  return QMC_OK;
+}
+
+qmc_status qmc_workspace_size(qmc_points p, int32_t op, int32_t t, const qmc_integrand *f,
+                              int32_t prec, size_t *bytes) {
+  if (qmc_status st = check_points(p)) return st;
+  if (!bytes) return fail(QMC_EINVAL, "bytes is null");
+  if (op < kOpMatvec || op > kOpGrad) return fail(QMC_EINVAL, "unknown op %d", op);
+  if (t < 1) return fail(QMC_EINVAL, "t = %d must be >= 1", t);
+  if (prec != QMC_FP32 && prec != QMC_SPLIT_BF16X3) return fail(QMC_EINVAL, "unknown precision %d", prec);
+  qmc_integrand dflt{QMC_G_ID, 0.0, QMC_H_ID, 0.0};
+  if (op != kOpMatvec) {
+    if (qmc_status st = check_integrand(f)) return st;
+  } else {
+    f = &dflt;
+  }
+  Work wk;
+  *bytes = carve(p->G, op, t, f, op == kOpMatvec ? 1 : p->G.R, nullptr, wk);
+  return QMC_OK;
+}
+
+qmc_status qmc_reduced_matvec(qmc_points p, int32_t r, const float *A, int32_t t, int64_t lda,
+                              int32_t prec, float *Y, int64_t ldy, void *workspace,
+                              size_t workspace_bytes, void *stream) {
+  using namespace qmc;
+  if (qmc_status st = check_points(p)) return st;
+  if (qmc_status st = check_matrix(A, t, lda, prec)) return st;
+  if (r < 0 || r >= p->G.R) return fail(QMC_EINVAL, "r = %d outside [0, %d)", r, p->G.R);
+  if (!Y) return fail(QMC_EINVAL, "Y is null");
+  if (ldy < t) return fail(QMC_EINVAL, "ldy = %lld < t = %d", (long long)ldy, t);
+  DeviceGuard dg(p->device);
+  hipStream_t st = (hipStream_t)stream;
+  const qmc_integrand fid{QMC_G_ID, 0.0, QMC_H_ID, 0.0};
+  Work wk;
+  const size_t need = carve(p->G, kOpMatvec, t, &fid, 1, nullptr, wk);
+  CallWorkspace own;
+  char *base = nullptr;
+  if (qmc_status s2 = get_workspace(p, need, workspace, workspace_bytes, st, own, base)) return s2;
+  carve(p->G, kOpMatvec, t, &fid, 1, base, wk);
+  const int64_t ldu = round_up(t, kTileT);
+  const Geometry &G = p->G;
+  QMC_HIP(launch_tables(G, p->D, r, 1, wk.tables, st), "tables launch");
+  QMC_HIP(launch_levels(G, prec, wk.tables, 1, A, t, lda, wk.U, ldu, st), "levels launch");
+  LeafOut o{};
+  o.Y = Y;
+  o.ldy = ldy;
+  QMC_HIP(launch_leaf(G, kModeStoreY, fid, wk.tables, wk.U, 1, r, A, t, lda, ldu, leaf_plan(G, t, 1, kModeStoreY), o, st),
+          "leaf launch");
+  return QMC_OK;
+}
+
+static qmc_status estimate_impl(qmc_points p, const float *A, int32_t t, int64_t lda,
+                                const qmc_integrand *f, int32_t prec, double *Q, float *dA,
+                                void *workspace, size_t workspace_bytes, void *stream) {
+  using namespace qmc;
+  if (qmc_status st = check_points(p)) return st;
+  if (qmc_status st = check_matrix(A, t, lda, prec)) return st;
+  if (qmc_status st = check_integrand(f)) return st;
+  if (!Q) return fail(QMC_EINVAL, "Q is null");
+  const bool grad = dA != nullptr;
+  DeviceGuard dg(p->device);
+  hipStream_t st = (hipStream_t)stream;
+  const Geometry &G = p->G;
+  const int nr = G.R;
+  const int op = grad ? kOpGrad : kOpEstimate;
+  Work wk;
+  const size_t need = carve(G, op, t, f, nr, nullptr, wk);
+  CallWorkspace own;
+  char *base = nullptr;
+  if (qmc_status s2 = get_workspace(p, need, workspace, workspace_bytes, st, own, base)) return s2;
+  carve(G, op, t, f, nr, base, wk);
+  const int64_t ldu = round_up(t, kTileT);
+  const int tct = (int)ceil_div(t, kTileT);
+  const LeafPlan lp = leaf_plan(G, t, nr, kModeSum);
+  const LeafPlan lg = leaf_plan(G, t, nr, kModeGrad);
+  const bool sep = f->h == QMC_H_ID;
+  const double inv_nt = 1.0 / ((double)G.N * (double)t);
+
+  QMC_HIP(launch_tables(G, p->D, 0, nr, wk.tables, st), "tables launch");
+  QMC_HIP(launch_levels(G, prec, wk.tables, nr, A, t, lda, wk.U, ldu, st), "levels launch");
+  LeafOut o{};
+  if (sep) {
+    if (!grad) {
+      o.partial = wk.partial;
+      QMC_HIP(launch_leaf(G, kModeSum, *f, wk.tables, wk.U, nr, 0, A, t, lda, ldu, lp, o, st), "leaf launch");
+      QMC_HIP(launch_reduce(wk.partial, nr, (int64_t)lp.gx * tct, inv_nt, Q, st), "reduce launch");
+      return QMC_OK;
+    }
+  } else {
+    // per-point sums over all columns, then h and the mean
+    o.ppart = wk.ppart;
+    QMC_HIP(launch_leaf(G, kModePoint, *f, wk.tables, wk.U, nr, 0, A, t, lda, ldu, lp, o, st), "leaf launch");
+    const int64_t blocks = point_h_blocks(G);
+    QMC_HIP(launch_point_h(G, *f, wk.ppart, nr, tct, t, wk.ppartial, blocks, grad ? wk.hd : nullptr,
+                           1.0, st),
+            "point h launch");
+    QMC_HIP(launch_reduce(wk.ppartial, nr, blocks, 1.0 / (double)G.N, Q, st), "reduce launch");
+    if (!grad) return QMC_OK;
+  }
+  // adjoint: G_ki = h'(u_k) g'(y_ki) / (N t)
+  LeafOut g{};
+  g.partial = wk.partial;
+  g.dApart = wk.dlow;
+  g.Sroot = wk.S;
+  g.hd = sep ? nullptr : wk.hd;
+  g.gscale = inv_nt;
+  QMC_HIP(launch_leaf(G, kModeGrad, *f, wk.tables, wk.U, nr, 0, A, t, lda, ldu, lg, g, st), "adjoint leaf launch");
+  if (sep) QMC_HIP(launch_reduce(wk.partial, nr, (int64_t)lg.gx * tct, inv_nt, Q, st), "reduce launch");
+  QMC_HIP(launch_fold(G, nr, wk.S, t, ldu, st), "fold launch");
+  QMC_HIP(launch_levels_adj(G, prec, wk.tables, nr, wk.S, t, ldu, wk.dup, st), "adjoint levels launch");
+  QMC_HIP(launch_combine(G, wk.dlow, lg.gx, tct, wk.dup, nr, t, ldu, dA, st), "combine launch");
+  return QMC_OK;
+}
+
+qmc_status qmc_estimate(qmc_points p, const float *A, int32_t t, int64_t lda, const qmc_integrand *f,
+                        int32_t prec, double *Q, void *workspace, size_t workspace_bytes, void *stream) {
+  return estimate_impl(p, A, t, lda, f, prec, Q, nullptr, workspace, workspace_bytes, stream);
+}
+
+qmc_status qmc_estimate_grad(qmc_points p, const float *A, int32_t t, int64_t lda,
+                             const qmc_integrand *f, int32_t prec, double *Q, float *dA,
+                             void *workspace, size_t workspace_bytes, void *stream) {
+  if (!dA) return fail(QMC_EINVAL, "dA is null");
+  return estimate_impl(p, A, t, lda, f, prec, Q, dA, workspace, workspace_bytes, stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,146 @@
+// Internal definitions shared by the HIP sources of libqmcred (not installed).
+//
+// Level structure.  With w non-decreasing, the coordinates with
+// min(w_j, m) = I form one contiguous block G_I = [j0, j0 + tau) of rows of A
+// (the groups of Algorithm 2).  Level I has n_I = 2^{m-I} distinct values per
+// coordinate.  The planner picks a split level L' (at most 6):
+//   * upper levels I >= L' are evaluated as small dense products
+//     U_I = X~_I A_I (n_I x t) on the matrix cores, one grouped launch;
+//   * lower levels I < L' are evaluated inside the fused leaf kernel: a point
+//     k = rho + c n_{L'} (rho < n_{L'}, c < 2^{L'}) is a leaf of the subtree
+//     rooted at residue rho, and the partial sums of the cascade
+//     P_I = tile(P_{I+1}) + X~_I A_I (Algorithm 2) are formed node by node.
+//
+// Point tables per randomisation r (FP32, sum_j n_j values in total):
+//   lower part  one record of S_rec floats per subtree root rho < n_{L'}:
+//               for I = L'-1 down to 0, for j in G_I, for c < 2^{L'-I}:
+//               value_j(rho + c n_{L'}).  A wave reads a record with scalar
+//               loads: every lane (column) needs the same values.
+//   upper part  for I >= L': X~_I row-major n_I x tau_I (K-contiguous).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "qmcred.h"
+
+namespace qmc {
+
+constexpr int kMaxM = 24;
+constexpr int kMaxLevels = kMaxM + 1;
+constexpr int kMaxSplit = 6;       // at most 64 leaves per subtree
+constexpr int kTileT = 64;         // columns per wave in the leaf kernels
+constexpr int kMaxLowRows = 64;    // rows of A kept in LDS by the leaf kernels
+
+struct Level {
+  int32_t tau;     // coordinates in the level
+  int32_t j0;      // first coordinate
+  int32_t nb;      // n_I = 1 << nb
+  int32_t pad;
+  int64_t off;     // lower level: offset inside a subtree record; upper: offset in the table
+  int64_t uoff;    // upper level: first row of U_I inside the per-shift U buffer
+};
+
+// Everything a kernel needs to know about the point set (passed by value).
+struct Geometry {
+  int32_t m, s, kind, rand, map, R;
+  int32_t split;         // L'
+  int32_t jlow;          // rows 0..jlow-1 of A belong to the lower levels
+  int32_t nup;           // number of upper levels with tau > 0
+  int32_t up[kMaxLevels];  // their indices I, increasing
+  int64_t N;
+  int64_t rec;           // floats per subtree record
+  int64_t nsub;          // n_{L'}: subtree roots
+  int64_t lower_total;   // nsub * rec
+  int64_t table_total;   // floats per shift = sum_j n_j
+  int64_t urows;         // rows of the U buffer per shift = sum over upper levels of n_I
+  Level lev[kMaxLevels];
+};
+
+// Device-side copy of the generators and shifts.
+struct DevSpec {
+  const uint32_t *gen;     // lattice/poly: [s]; net: [s*m] column words
+  const int32_t *nbj;      // [s] m - min(w_j, m)
+  const double *shift;     // [R*s]
+  const uint64_t *dshift;  // [R*s]
+};
+
+// Per-call timing hook (no-op unless enabled).
+struct LaunchTimer {
+  const char *name;
+  hipStream_t st;
+  void *ev0 = nullptr;
+  LaunchTimer(const char *n, hipStream_t s);
+  ~LaunchTimer();
+};
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
+
+// ---------------------------------------------------------------- launchers
+// Each returns hipSuccess or the launch error.
+
+// Point tables (FP32) for shifts [r0, r0 + nr): out[(r - r0) * table_total + e].
+hipError_t launch_tables(const Geometry &G, const DevSpec &D, int r0, int nr, float *out,
+                         hipStream_t st);
+// Distinct FP64 values of coordinate j for shift r.
+hipError_t launch_point_values(const Geometry &G, const DevSpec &D, int r, int j, double *out,
+                               hipStream_t st);
+// Dense FP32 point matrix for shift r.
+hipError_t launch_point_matrix(const Geometry &G, const DevSpec &D, int r, float *X, int64_t ldx,
+                               hipStream_t st);
+
+// Grouped upper-level products U_I = X~_I A_I for shifts [0, nr) of the table buffer.
+hipError_t launch_levels(const Geometry &G, int prec, const float *tables, int nr, const float *A,
+                         int t, int64_t lda, float *U, int64_t ldu, hipStream_t st);
+
+// Adjoint of the upper levels: dA_I = X~_I^T S_I; S pyramid rows as in fold.
+hipError_t launch_levels_adj(const Geometry &G, int prec, const float *tables, int nr,
+                             const float *S, int t, int64_t ldu, float *part, hipStream_t st);
+int64_t levels_adj_part_floats(const Geometry &G, int t, int64_t ldu);
+
+// Fold of the subtree-root sums over the upper levels (S_{I+1} from S_I).
+hipError_t launch_fold(const Geometry &G, int nr, float *S, int t, int64_t ldu, hipStream_t st);
+
+enum LeafMode { kModeSum = 0, kModePoint = 1, kModeStoreY = 2, kModeGrad = 3 };
+
+struct LeafOut {
+  double *partial;     // kModeSum / kModeGrad: [nr][gx][tct] FP64 sums of g
+  float *ppart;        // kModePoint: [nr][tct][N] per-point sums over a column tile
+  float *Y;            // kModeStoreY
+  int64_t ldy;
+  float *dApart;       // kModeGrad: [nr][gx][tct][jlow][64] lower-level dA partials
+  float *Sroot;        // kModeGrad: [nr][nsub][ldu] subtree-root sums of G
+  const float *hd;     // kModeGrad, non-separable h: [nr][N] per-point factor h'(u)
+  double gscale;       // kModeGrad: factor of g' (1/(N t) for separable h)
+};
+
+struct LeafPlan {
+  int gx;              // workgroups along the subtree axis
+  int spw;             // subtrees per wave
+  int nw;              // waves per workgroup
+};
+LeafPlan leaf_plan(const Geometry &G, int t, int nr, int mode);
+
+hipError_t launch_leaf(const Geometry &G, int mode, const qmc_integrand &f, const float *tables,
+                       const float *U, int nr, int r0, const float *A, int t, int64_t lda,
+                       int64_t ldu, const LeafPlan &lp, const LeafOut &o, hipStream_t st);
+
+// Q[r] = scale * sum of partial[r][*] (fixed order, compensated).
+hipError_t launch_reduce(const double *partial, int nr, int64_t per, double scale, double *Q,
+                         hipStream_t st);
+// Per-point h: partial[r][blk] = sum over points of h(t^-1 sum_ct ppart), and
+// optionally hd[r][k] = h'(u_k) * hscale.
+hipError_t launch_point_h(const Geometry &G, const qmc_integrand &f, const float *ppart, int nr,
+                          int tct, int t, double *partial, int64_t blocks, float *hd,
+                          double hscale, hipStream_t st);
+int64_t point_h_blocks(const Geometry &G);
+
+// dA[r][j][i] = sum of the lower partials (rows j < jlow) or of the upper
+// partials (rows of the upper levels), FP64 accumulation, FP32 result.
+hipError_t launch_combine(const Geometry &G, const float *dApart_low, int gx, int tct,
+                          const float *dApart_up, int nr, int t, int64_t ldu, float *dA,
+                          hipStream_t st);
+
+}  // namespace qmc

@@ -1,0 +1,160 @@
+// Point-table generation (the distinct values of every coordinate).
+//
+// For coordinate j with n_j = 2^nb distinct values the integer c of the value
+// c / 2^nb at residue rho < n_j is
+//   lattice       c = rho * z'_j mod 2^nb                      (Section 1.3)
+//   poly lattice  c = int(rho(x) g'_j(x) mod x^nb)             (Section 1.1, nu)
+//   digital net   digits y_p = sum_q C_{p,q} rho_q (p <= nb)   (eq. def:digital,
+//                 c = sum_p y_p 2^{nb-p}                        reduced_genmat_net2)
+// then the randomisation and the map are applied in FP64 (Section 1.2,
+// Section 2.3) and the result is rounded once to FP32.  All integer work is
+// exact; the FP64 sequence is fixed (no contraction) so tables are
+// reproducible bit for bit.
+#include "qmc_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace qmc {
+
+__device__ __forceinline__ uint32_t value_int(const Geometry &G, const uint32_t *__restrict__ gen,
+                                              int j, uint32_t rho, int nb) {
+  if (nb == 0) return 0u;
+  const uint32_t mask = (nb >= 32) ? 0xffffffffu : ((1u << nb) - 1u);
+  if (G.kind == QMC_LATTICE) return (rho * gen[j]) & mask;
+  if (G.kind == QMC_POLY_LATTICE) {
+    const uint32_t g = gen[j];
+    uint32_t acc = 0;
+    for (int i = 0; i < nb; ++i)
+      if ((rho >> i) & 1u) acc ^= g << i;
+    return acc & mask;
+  }
+  const uint32_t *col = gen + (size_t)j * G.m;
+  uint32_t y = 0;
+  for (int q = 0; q < nb; ++q)
+    if ((rho >> q) & 1u) y ^= col[q];
+  y &= mask;  // rows p > nb of the reduced matrix are zero
+  return __builtin_bitreverse32(y) >> (32 - nb);
+}
+
+__device__ __forceinline__ double value_f64(const Geometry &G, const DevSpec &D, int r, int j,
+                                            uint32_t rho, int nb) {
+  const uint32_t c = value_int(G, D.gen, j, rho, nb);
+  double x;
+  if (G.rand == QMC_DIGITAL_SHIFT) {
+    const uint64_t U = ((uint64_t)c << (52 - nb)) ^ D.dshift[(size_t)r * G.s + j];
+    x = (double)(2 * U + 1) * 0x1p-53;  // exact
+  } else {
+    x = (double)c * __builtin_ldexp(1.0, -nb);  // exact
+    if (G.rand == QMC_RANDOM_SHIFT) {
+      x = __dadd_rn(x, D.shift[(size_t)r * G.s + j]);
+      if (x >= 1.0) x = __dsub_rn(x, 1.0);
+    }
+  }
+  switch (G.map) {
+    case QMC_MAP_CENTER: return __dsub_rn(x, 0.5);
+    case QMC_MAP_INVNORM: return normcdfinv(x);
+    case QMC_MAP_TENT: return __dsub_rn(1.0, fabs(__dsub_rn(1.0, __dmul_rn(2.0, x))));
+    default: return x;
+  }
+}
+
+// Map a table entry e (per shift) to (coordinate j, residue rho, nb).
+__device__ __forceinline__ void locate(const Geometry &G, int64_t e, int &j, uint32_t &rho, int &nb) {
+  if (e < G.lower_total) {
+    const int64_t sub = e / G.rec;
+    const int64_t o = e - sub * G.rec;
+    for (int I = G.split - 1; I >= 0; --I) {
+      const Level &L = G.lev[I];
+      const int64_t nc = int64_t(1) << (G.split - I);
+      if (L.tau > 0 && o >= L.off && o < L.off + L.tau * nc) {
+        const int64_t q = o - L.off;
+        j = L.j0 + (int)(q / nc);
+        rho = (uint32_t)(sub + (q % nc) * G.nsub);
+        nb = L.nb;
+        return;
+      }
+    }
+  } else {
+    const int64_t q = e - G.lower_total;
+    for (int u = 0; u < G.nup; ++u) {
+      const Level &L = G.lev[G.up[u]];
+      const int64_t n = int64_t(1) << L.nb;
+      if (q >= L.off && q < L.off + n * L.tau) {
+        const int64_t o = q - L.off;
+        rho = (uint32_t)(o / L.tau);
+        j = L.j0 + (int)(o % L.tau);
+        nb = L.nb;
+        return;
+      }
+    }
+  }
+  j = 0; rho = 0; nb = 0;  // unreachable for e < table_total
+}
+
+__global__ void tables_kernel(Geometry G, DevSpec D, int r0, int nr, float *__restrict__ out) {
+  const int64_t total = G.table_total * nr;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(idx / G.table_total);
+    const int64_t e = idx - (int64_t)r * G.table_total;
+    int j, nb;
+    uint32_t rho;
+    locate(G, e, j, rho, nb);
+    out[idx] = (float)value_f64(G, D, r0 + r, j, rho, nb);
+  }
+}
+
+__global__ void values_kernel(Geometry G, DevSpec D, int r, int j, int nb, double *__restrict__ out) {
+  const uint32_t n = 1u << nb;
+  for (uint32_t rho = blockIdx.x * blockDim.x + threadIdx.x; rho < n; rho += gridDim.x * blockDim.x)
+    out[rho] = value_f64(G, D, r, j, rho, nb);
+}
+
+__global__ void point_matrix_kernel(Geometry G, DevSpec D, int r, float *__restrict__ X, int64_t ldx) {
+  const int64_t total = G.N * G.s;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t k = idx / G.s;
+    const int j = (int)(idx - k * G.s);
+    const int nb = D.nbj[j];
+    const uint32_t rho = (uint32_t)(k & ((int64_t(1) << nb) - 1));
+    X[k * ldx + j] = (float)value_f64(G, D, r, j, rho, nb);
+  }
+}
+
+static int grid_for(int64_t work, int threads) {
+  int64_t g = ceil_div(work, threads);
+  if (g > 65536) g = 65536;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+hipError_t launch_tables(const Geometry &G, const DevSpec &D, int r0, int nr, float *out,
+                         hipStream_t st) {
+  LaunchTimer tm("tables", st);
+  const int64_t work = G.table_total * nr;
+  hipLaunchKernelGGL(tables_kernel, dim3(grid_for(work, 256)), dim3(256), 0, st, G, D, r0, nr, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_point_values(const Geometry &G, const DevSpec &D, int r, int j, double *out,
+                               hipStream_t st) {
+  LaunchTimer tm("points", st);
+  // nb of coordinate j from the level table
+  int nb = 0;
+  for (int I = 0; I <= G.m; ++I)
+    if (j >= G.lev[I].j0 && j < G.lev[I].j0 + G.lev[I].tau) nb = G.lev[I].nb;
+  hipLaunchKernelGGL(values_kernel, dim3(grid_for(int64_t(1) << nb, 256)), dim3(256), 0, st, G, D,
+                     r, j, nb, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_point_matrix(const Geometry &G, const DevSpec &D, int r, float *X, int64_t ldx,
+                               hipStream_t st) {
+  LaunchTimer tm("points", st);
+  hipLaunchKernelGGL(point_matrix_kernel, dim3(grid_for(G.N * G.s, 256)), dim3(256), 0, st, G, D, r,
+                     X, ldx);
+  return hipGetLastError();
+}
+
+}  // namespace qmc

@@ -1,0 +1,161 @@
+"""Host-side tests of the C ABI (no GPU needed): symbols, status codes, validation.
+
+Every argument check of qmc_points_init runs on the host before any device
+call, so each error path is exercised here without a GPU.
+"""
+import ctypes as ct
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2305_11645_amd as q
+from paper_2305_11645_amd import _lib
+from paper_2305_11645_amd import inputs as I
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "qmcred.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(qmc_[a-z_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol():
+    L = _lib.load()
+    names = declared_functions()
+    assert len(names) >= 14
+    assert sorted(names) == sorted(_lib.EXPORTS)
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_status_strings():
+    L = _lib.load()
+    for code, text in [(0, b"success"), (1, b"invalid argument"), (2, b"unsupported"),
+                       (3, b"out of memory"), (4, b"device error")]:
+        assert L.qmc_status_string(code) == text
+
+
+def _spec(wl, **over):
+    arrs = {}
+    w = np.ascontiguousarray(over.pop("w", wl.w), dtype=np.int32)
+    gen = np.ascontiguousarray(over.pop("gen", wl.gen), dtype=np.uint64)
+    shift = over.pop("shift", wl.shift)
+    dshift = over.pop("dshift", wl.dshift)
+    arrs["w"], arrs["gen"] = w, gen
+    sp = _lib.PointSpec(b=over.pop("b", 2), m=over.pop("m", wl.m), s=over.pop("s", wl.s),
+                        kind=over.pop("kind", wl.kind),
+                        w=w.ctypes.data_as(ct.POINTER(ct.c_int32)),
+                        gen=gen.ctypes.data_as(ct.POINTER(ct.c_uint64)),
+                        rand=over.pop("rand", wl.rand), R=over.pop("R", wl.R), map=over.pop("map", wl.map))
+    if shift is not None:
+        arrs["shift"] = np.ascontiguousarray(shift, dtype=np.float64)
+        sp.shift = arrs["shift"].ctypes.data_as(ct.POINTER(ct.c_double))
+    if dshift is not None:
+        arrs["dshift"] = np.ascontiguousarray(dshift, dtype=np.uint64)
+        sp.dshift = arrs["dshift"].ctypes.data_as(ct.POINTER(ct.c_uint64))
+    assert not over, over
+    return sp, arrs
+
+
+def _init_status(sp):
+    L = _lib.load()
+    h = ct.c_void_p()
+    st = L.qmc_points_init(ct.byref(h), ct.byref(sp))
+    if st == 0:
+        L.qmc_points_free(h)
+    return st, L.qmc_last_error().decode()
+
+
+def lat(**kw):
+    return I.make_custom(kind=I.LATTICE, m=8, s=10, t=4, w=I.w_log2(10, 9), rand=I.RANDOM_SHIFT, R=2, **kw)
+
+
+CASES = [
+    ("b not prime", lambda wl: _spec(wl, b=4), 1),
+    ("b odd prime", lambda wl: _spec(wl, b=3), 2),
+    ("m too large", lambda wl: _spec(wl, m=25), 2),
+    ("m zero", lambda wl: _spec(wl, m=0), 2),
+    ("w0 nonzero", lambda wl: _spec(wl, w=np.r_[1, wl.w[1:]]), 1),
+    ("w decreasing", lambda wl: _spec(wl, w=np.r_[wl.w[:5], [0] * 5]), 1),
+    ("even generator", lambda wl: _spec(wl, gen=np.r_[[2], wl.gen[1:]]), 1),
+    ("generator too big", lambda wl: _spec(wl, gen=np.r_[[2 ** 9 + 1], wl.gen[1:]]), 1),
+    ("shift out of range", lambda wl: _spec(wl, shift=np.full((2, 10), 1.0)), 1),
+    ("negative R", lambda wl: _spec(wl, R=0), 1),
+    ("unknown kind", lambda wl: _spec(wl, kind=7), 1),
+    ("unknown map", lambda wl: _spec(wl, map=9), 1),
+    ("invnorm without shift", lambda wl: _spec(wl, rand=I.NO_SHIFT, R=1, shift=None, map=I.MAP_INVNORM), 1),
+    ("R > 1 without shift", lambda wl: _spec(wl, rand=I.NO_SHIFT, R=2), 1),
+]
+
+
+@pytest.mark.parametrize("name,make,code", CASES, ids=[c[0] for c in CASES])
+def test_points_init_validation(name, make, code):
+    sp, keep = make(lat())
+    st, msg = _init_status(sp)
+    assert st == code, (name, st, msg)
+    assert msg
+
+
+def test_digital_shift_range():
+    wl = I.make_custom(kind=I.DIGITAL_NET, m=6, s=5, t=3, w=[0, 1, 2, 3, 3], rand=I.DIGITAL_SHIFT, R=1)
+    sp, keep = _spec(wl, dshift=np.full((1, 5), 1 << 52, dtype=np.uint64))
+    assert _init_status(sp)[0] == 1
+
+
+def test_net_not_periodic_is_unsupported():
+    """An upper-triangular (Sobol'-type) matrix keeps columns beyond n_j after the
+    row reduction, so the points are not periodic in k: unsupported."""
+    m, s = 6, 3
+    words = []
+    for j in range(s):
+        for qq in range(m):
+            words.append(sum(1 << p for p in range(qq + 1)))  # C_{p,q} = 1 for p <= q
+    wl = I.make_custom(kind=I.DIGITAL_NET, m=m, s=s, t=2, w=[0, 2, 3], rand=I.NO_SHIFT)
+    sp, keep = _spec(wl, gen=np.array(words, dtype=np.uint64))
+    assert _init_status(sp)[0] == 2
+
+
+def test_net_word_beyond_m():
+    wl = I.make_custom(kind=I.DIGITAL_NET, m=5, s=2, t=2, w=[0, 1], rand=I.NO_SHIFT)
+    g = wl.gen.copy()
+    g[0] |= np.uint64(1 << 7)
+    sp, keep = _spec(wl, gen=g)
+    assert _init_status(sp)[0] == 1
+
+
+def test_valid_spec_without_device():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible: the no-device path is not reachable")
+    sp, keep = _spec(lat())
+    st, msg = _init_status(sp)
+    assert st == 4 and "device" in msg
+
+
+def test_null_handle_calls():
+    L = _lib.load()
+    f = _lib.Integrand(g=1, c=1.0, h=0, K=0.0)
+    n = ct.c_size_t()
+    assert L.qmc_workspace_size(None, 1, 8, ct.byref(f), 0, ct.byref(n)) == 1
+    assert L.qmc_estimate(None, None, 8, 8, ct.byref(f), 0, None, None, 0, None) == 1
+    assert L.qmc_reduced_matvec(None, 0, None, 8, 8, 0, None, 8, None, 0, None) == 1
+    assert L.qmc_estimate_grad(None, None, 8, 8, ct.byref(f), 0, None, None, None, 0, None) == 1
+    assert L.qmc_point_values(None, 0, 0, None, None) == 1
+    assert L.qmc_points_free(None) == 0
+
+
+def test_python_errors_are_typed():
+    sp, keep = _spec(lat(), b=4)
+    with pytest.raises(q.QMCInvalid):
+        _lib.check(_lib.load().qmc_points_init(ct.byref(ct.c_void_p()), ct.byref(sp)))
+
+
+def test_timing_api_on_host():
+    q.timing.enable(True)
+    q.timing.reset()
+    assert q.timing.read("leaf") == (0.0, 0)
+    q.timing.enable(False)

@@ -1,0 +1,318 @@
+"""GPU parity: the HIP library against the FP64 oracle, through the C ABI.
+
+Small cases compare every output element with the oracle (several tiles and a
+ragged column tail); the five full-size workloads compare sampled outputs that
+the oracle computes one by one, and the estimates against oracle values stored
+by tests/golden/make_expected.py (a script that calls only the oracle).
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import paper_2305_11645_amd as q
+from gpu_common import elementwise_bound, oracle_rows, oracle_tables, to_dev, torch_cuda
+from paper_2305_11645_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+KINDS = [I.LATTICE, I.POLY_LATTICE, I.DIGITAL_NET]
+RANDS = [I.NO_SHIFT, I.RANDOM_SHIFT, I.DIGITAL_SHIFT]
+Q_TOL = 1e-6      # relative error target on every estimate
+
+
+def small(kind, rand, mp=I.MAP_ID, m=9, s=40, t=100, R=2, seed=3, w=None, g=I.G_COS, h=I.H_ID,
+          K=0.0, c=1.0, A_scale=0.3):
+    if w is None:
+        w = I.w_log2(s, m + 1)
+    return I.make_custom(kind=kind, m=m, s=s, t=t, w=w, rand=rand, R=R, map=mp, g=g, h=h, K=K, c=c,
+                         seed=seed, A_scale=A_scale)
+
+
+# ------------------------------------------------------------------ tables
+
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("rand", RANDS)
+@pytest.mark.parametrize("mp", [I.MAP_ID, I.MAP_CENTER, I.MAP_TENT, I.MAP_INVNORM])
+def test_tables_bit_exact(kind, rand, mp):
+    """Distinct values (FP64) equal the oracle's bit for bit; the inverse-normal
+    map (device normcdfinv vs AS241) agrees to a few ulp."""
+    if mp == I.MAP_INVNORM and rand == I.NO_SHIFT:
+        pytest.skip("the inverse-normal map requires a shift")
+    torch = torch_cuda()
+    wl = small(kind, rand, mp, m=10, s=24)
+    pts = q.Points.from_workload(wl)
+    for r in range(wl.R):
+        ref = oracle_tables(wl, r)
+        for j in range(wl.s):
+            got = q.point_values(pts, r, j).cpu().numpy()
+            if mp == I.MAP_INVNORM:
+                np.testing.assert_allclose(got, ref[j], rtol=1e-14, atol=0)
+            else:
+                np.testing.assert_array_equal(got, ref[j])
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_point_matrix_matches_unreduced(kind):
+    """The FP32 point matrix equals the FP32 rounding of the oracle's unreduced X."""
+    from oracle import oracle as O
+    torch_cuda()
+    wl = small(kind, I.RANDOM_SHIFT, m=9, s=30)
+    pts = q.Points.from_workload(wl)
+    for r in range(wl.R):
+        X = q.point_matrix(pts, r).cpu().numpy()
+        np.testing.assert_array_equal(X, O.point_matrix_unreduced(wl, r).astype(np.float32))
+
+
+# ------------------------------------------------------------------ matvec
+
+def _check_Y(wl, Y, r, prec):
+    from oracle import oracle as O
+    Yo = O.reduced_matvec(wl, r)
+    X = O.point_matrix_unreduced(wl, r)
+    mag = np.abs(X) @ np.abs(wl.A.astype(np.float64))
+    err = np.abs(Y.astype(np.float64) - Yo)
+    bound = elementwise_bound(wl, prec) * mag + 1e-30
+    worst = float(np.max(err / bound))
+    assert worst <= 1.0, f"element error {worst:.3g} x bound"
+    return float(np.linalg.norm(Y - Yo) / np.linalg.norm(Yo))
+
+
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("rand", RANDS)
+@pytest.mark.parametrize("prec", [I.FP32, I.SPLIT_BF16X3])
+def test_matvec_elementwise(kind, rand, prec):
+    """Y = X A for every element within the FP32 (or split-bf16) error bound.
+    t = 100 spans two 64-column tiles with a ragged tail; m = 9 gives several
+    subtrees and several upper levels."""
+    torch = torch_cuda()
+    mp = I.MAP_INVNORM if rand == I.DIGITAL_SHIFT else I.MAP_ID
+    wl = small(kind, rand, mp)
+    pts = q.Points.from_workload(wl)
+    A = to_dev(wl.A, torch)
+    for r in range(wl.R):
+        Y = q.reduced_matvec(pts, A, r=r, prec=prec).cpu().numpy()
+        rel = _check_Y(wl, Y, r, prec)
+        assert rel < (1e-6 if prec == I.FP32 else 2e-4)
+
+
+@pytest.mark.parametrize("split_case", ["deep", "flat", "tiny", "wide"])
+def test_matvec_shapes(split_case):
+    """Level structures that exercise the planner: many lower levels, w = 0
+    everywhere (all coordinates in level 0), m below the split cap, and
+    coordinates with w_j >= m (constant columns)."""
+    torch = torch_cuda()
+    if split_case == "deep":
+        wl = small(I.LATTICE, I.RANDOM_SHIFT, m=12, s=70, t=64, w=I.w_log2(70, 12))
+    elif split_case == "flat":
+        wl = small(I.LATTICE, I.RANDOM_SHIFT, m=8, s=20, t=65, w=[0] * 20)
+    elif split_case == "tiny":
+        wl = small(I.DIGITAL_NET, I.DIGITAL_SHIFT, m=3, s=5, t=3, w=[0, 1, 1, 2, 5])
+    else:
+        wl = small(I.POLY_LATTICE, I.NO_SHIFT, m=7, s=150, t=130, w=I.w_log2(150, 9))
+    pts = q.Points.from_workload(wl)
+    A = to_dev(wl.A, torch)
+    Y = q.reduced_matvec(pts, A, r=0).cpu().numpy()
+    _check_Y(wl, Y, 0, I.FP32)
+
+
+def test_matvec_identity_is_point_matrix():
+    """A = I_s gives Y = X exactly (FP32 path)."""
+    torch = torch_cuda()
+    wl = small(I.LATTICE, I.RANDOM_SHIFT, m=10, s=64, t=64)
+    pts = q.Points.from_workload(wl)
+    A = torch.eye(64, dtype=torch.float32, device="cuda")
+    Y = q.reduced_matvec(pts, A, r=1)
+    X = q.point_matrix(pts, 1)
+    assert torch.equal(Y, X)
+
+
+def test_matvec_strided_A_and_Y():
+    """Leading dimensions larger than t on both A and Y."""
+    torch = torch_cuda()
+    wl = small(I.LATTICE, I.RANDOM_SHIFT, m=9, s=40, t=70)
+    pts = q.Points.from_workload(wl)
+    Abig = torch.zeros((40, 96), dtype=torch.float32, device="cuda")
+    Abig[:, :70] = to_dev(wl.A, torch)
+    Ybig = torch.full((wl.N, 128), 7.0, dtype=torch.float32, device="cuda")
+    q.reduced_matvec(pts, Abig[:, :70], r=0, Y=Ybig[:, :70])
+    Y = Ybig.cpu().numpy()
+    assert np.all(Y[:, 70:] == 7.0)
+    _check_Y(wl, Y[:, :70], 0, I.FP32)
+
+
+# ------------------------------------------------------------------ estimate
+
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("g,h,c", [(I.G_COS, I.H_ID, 1.0), (I.G_EXP, I.H_ID, -0.7),
+                                   (I.G_EXP, I.H_CALL, 0.2), (I.G_ID, I.H_ID, 1.0)])
+def test_estimate_small(kind, g, h, c):
+    """Q[r] against the oracle to 1e-6 relative for every integrand family."""
+    from oracle import oracle as O
+    torch = torch_cuda()
+    rand = I.DIGITAL_SHIFT if kind == I.DIGITAL_NET else I.RANDOM_SHIFT
+    K = 1.0 if h == I.H_CALL else 0.0
+    wl = small(kind, rand, g=g, h=h, c=c, K=K, R=3)
+    pts = q.Points.from_workload(wl)
+    A = to_dev(wl.A, torch)
+    Q = q.estimate(pts, A, q.Integrand_.of(wl)).cpu().numpy()
+    Qo, _ = O.estimate(wl)
+    scale = np.maximum(np.abs(Qo), 1e-3)
+    assert np.all(np.abs(Q - Qo) <= Q_TOL * scale), (Q, Qo)
+
+
+def test_estimate_linear_closed_form():
+    """g(y) = y, h = id: the exact closed form t^-1 sum_i sum_j a_ji mu_j holds
+    at any N; the GPU estimate matches it within FP32 accumulation error."""
+    torch = torch_cuda()
+    wl = small(I.LATTICE, I.RANDOM_SHIFT, m=14, s=200, t=192, g=I.G_ID, R=4)
+    pts = q.Points.from_workload(wl)
+    Q = q.estimate(pts, to_dev(wl.A, torch), q.Integrand_.of(wl)).cpu().numpy()
+    A = wl.A.astype(np.float64)
+    for r in range(wl.R):
+        mu = []
+        for j in range(wl.s):
+            n = 2 ** (wl.m - min(int(wl.w[j]), wl.m))
+            mu.append((n - 1 + 2 * ((n * float(wl.shift[r, j])) % 1.0)) / (2 * n))
+        ref = float(np.mean(np.array(mu) @ A))
+        assert abs(Q[r] - ref) <= 1e-6 * max(abs(ref), float(np.mean(np.abs(A).sum(0))))
+
+
+def test_estimate_deterministic():
+    """Two runs are bitwise equal (fixed-order reductions, no float atomics)."""
+    torch = torch_cuda()
+    wl = I.make_config(2, m=13, R=4)
+    pts = q.Points.from_workload(wl)
+    A = to_dev(wl.A, torch)
+    f = q.Integrand_.of(wl)
+    Q1 = q.estimate(pts, A, f)
+    Q2 = q.estimate(pts, A, f)
+    assert torch.equal(Q1, Q2)
+
+
+def test_estimate_library_workspace():
+    """workspace = NULL: the library allocates a stream-ordered workspace itself."""
+    import ctypes as ct
+    torch = torch_cuda()
+    wl = small(I.LATTICE, I.RANDOM_SHIFT, R=2)
+    pts = q.Points.from_workload(wl)
+    A = to_dev(wl.A, torch)
+    f = q.Integrand_.of(wl)
+    Q = torch.empty(2, dtype=torch.float64, device="cuda")
+    L = q.load()
+    st = ct.c_void_p(torch.cuda.current_stream().cuda_stream)
+    q._lib.check(L.qmc_estimate(pts.handle, ct.c_void_p(A.data_ptr()), wl.t, wl.t, ct.byref(f.c_struct()),
+                                0, ct.c_void_p(Q.data_ptr()), None, 0, st))
+    assert torch.equal(Q, q.estimate(pts, A, f))
+
+
+# ------------------------------------------------------------------ gradient
+
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("g,h,c", [(I.G_COS, I.H_ID, 1.0), (I.G_EXP, I.H_CALL, 0.2)])
+def test_gradient_small(kind, g, h, c):
+    """dQ/dA against the oracle gradient, relative Frobenius <= 1e-6 per shift."""
+    from oracle import oracle as O
+    torch = torch_cuda()
+    rand = I.DIGITAL_SHIFT if kind == I.DIGITAL_NET else I.RANDOM_SHIFT
+    K = 1.0 if h == I.H_CALL else 0.0
+    wl = small(kind, rand, m=10, s=50, t=80, g=g, h=h, c=c, K=K, R=2)
+    pts = q.Points.from_workload(wl)
+    A = to_dev(wl.A, torch)
+    Q, dA = q.estimate_grad(pts, A, q.Integrand_.of(wl))
+    Qo, dAo = O.estimate_grad(wl)
+    Q, dA = Q.cpu().numpy(), dA.cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(Q - Qo) <= Q_TOL * np.maximum(np.abs(Qo), 1e-3))
+    for r in range(wl.R):
+        rel = np.linalg.norm(dA[r] - dAo[r]) / np.linalg.norm(dAo[r])
+        assert rel <= 1e-6, rel
+
+
+def test_autograd_matches_grad():
+    """QMCEstimate.backward returns sum_r gQ_r dQ_r/dA."""
+    torch = torch_cuda()
+    wl = small(I.LATTICE, I.RANDOM_SHIFT, R=3)
+    pts = q.Points.from_workload(wl)
+    A = to_dev(wl.A, torch).requires_grad_(True)
+    f = q.Integrand_.of(wl)
+    Q = q.QMCEstimate.apply(A, pts, f, I.FP32)
+    wts = torch.tensor([0.5, -1.0, 2.0], dtype=torch.float64, device="cuda")
+    (Q * wts).sum().backward()
+    _, dA = q.estimate_grad(pts, A.detach(), f)
+    ref = (wts.view(-1, 1, 1) * dA.double()).sum(0).float()
+    assert torch.allclose(A.grad, ref, rtol=1e-6, atol=1e-12)
+
+
+# ------------------------------------------------------------------ full-size workloads
+
+def _expected():
+    path = os.path.join(GOLDEN, "expected_full.json")
+    with open(path) as fh:
+        return json.load(fh)
+
+
+@pytest.mark.parametrize("c", [1, 2, 3, 4, 5])
+def test_full_config_estimate(c):
+    """Each workload at its full size, in the launch configuration the
+    benchmark times: Q[r] within 1e-6 relative of the stored oracle values."""
+    torch = torch_cuda()
+    exp = _expected()[f"C{c}"]
+    wl = I.make_config(c)
+    pts = q.Points.from_workload(wl)
+    A = to_dev(wl.A, torch)
+    for prec in exp["precisions"]:
+        Q = q.estimate(pts, A, q.Integrand_.of(wl), prec=prec).cpu().numpy()
+        Qo = np.array(exp["Q"])
+        n = len(Qo)
+        rel = np.abs(Q[:n] - Qo) / np.abs(Qo)
+        print(f"C{c} prec={prec} max rel err {rel.max():.3e}", flush=True)
+        assert rel.max() <= Q_TOL, (c, prec, rel)
+
+
+@pytest.mark.parametrize("c", [2, 3, 4, 5])
+def test_full_config_sampled_rows(c):
+    """qmc_reduced_matvec at full size: 48 sampled rows of Y = X A against the
+    oracle's FP64 rows (tables indexed by k mod n_j), element-wise bound."""
+    torch = torch_cuda()
+    wl = I.make_config(c)
+    pts = q.Points.from_workload(wl)
+    A = to_dev(wl.A, torch)
+    r = wl.R - 1
+    Y = q.reduced_matvec(pts, A, r=r, prec=I.FP32)
+    rng = np.random.default_rng(c)
+    ks = np.concatenate([[0, 1, wl.N - 1], rng.integers(0, wl.N, 45)])
+    Ys = Y[torch.from_numpy(ks).cuda()].cpu().numpy().astype(np.float64)
+    del Y
+    Yo, mag = oracle_rows(wl, r, ks)
+    err = np.abs(Ys - Yo) / (elementwise_bound(wl, I.FP32) * mag + 1e-30)
+    assert err.max() <= 1.0
+
+
+def test_full_config_gradient_columns():
+    """C5 gradient at full size: for separable f each column of dA depends only
+    on the same column of A, so the oracle computes a 64-column sample exactly
+    (rescaled by 64/t).  Relative Frobenius error <= 1e-6 on the sample."""
+    from oracle import oracle as O
+    torch = torch_cuda()
+    wl = I.make_config(5)
+    pts = q.Points.from_workload(wl)
+    A = to_dev(wl.A, torch)
+    Q, dA = q.estimate_grad(pts, A, q.Integrand_.of(wl))
+    cols = np.arange(3, wl.t, 16)[:64]
+    sub = I.make_config(5)
+    sub.A64 = np.ascontiguousarray(wl.A64[:, cols])
+    sub.t = len(cols)
+    _, dAo = O.estimate_grad(sub)
+    dAo = dAo[0] * (len(cols) / wl.t)
+    got = dA[0][:, torch.from_numpy(cols).cuda()].cpu().numpy().astype(np.float64)
+    rel = np.linalg.norm(got - dAo) / np.linalg.norm(dAo)
+    print(f"C5 gradient sample rel err {rel:.3e}", flush=True)
+    assert rel <= 1e-6
+    exp = _expected()["C5"]
+    assert abs(Q.cpu().numpy()[0] - exp["Q"][0]) <= Q_TOL * abs(exp["Q"][0])
