@@ -32,20 +32,31 @@ struct LeafArgs {
   int32_t gx, nw;
   int64_t lda, ldu, ldy;
   float gc;        // parameter c of g = exp(c y)
+  float gcl2;      // c log2(e)
   double gscale;   // factor of g' in the adjoint
 };
 
+// g and g' on the transcendental unit.  cos and sin: v_cos/v_sin take the
+// angle in revolutions; the argument y / (2 pi) is rounded once and reduced
+// exactly with v_fract, so the only error beyond the FP32 rounding already
+// present in y is that of the hardware approximation.  exp(c y) is
+// 2^(y c log2 e) on v_exp, with c log2 e precomputed.
+constexpr float kInv2Pi = 0.15915494309189533577f;
+
+__device__ __forceinline__ float rev(float y) { return __builtin_amdgcn_fractf(y * kInv2Pi); }
+
 template <int GF>
-__device__ __forceinline__ float g_val(float y, float c) {
-  if (GF == QMC_G_COS) return cosf(y);
-  if (GF == QMC_G_EXP) return expf(c * y);
+__device__ __forceinline__ float g_val(float y, float cl2) {
+  if (GF == QMC_G_COS) return __builtin_amdgcn_cosf(rev(y));
+  if (GF == QMC_G_EXP) return __builtin_amdgcn_exp2f(y * cl2);
   return y;
 }
 
+// derivative g'(y); c is the parameter of exp(c y)
 template <int GF>
-__device__ __forceinline__ float g_der(float y, float c) {
-  if (GF == QMC_G_COS) return -sinf(y);
-  if (GF == QMC_G_EXP) return c * expf(c * y);
+__device__ __forceinline__ float g_der(float y, float cl2, float c) {
+  if (GF == QMC_G_COS) return -__builtin_amdgcn_sinf(rev(y));
+  if (GF == QMC_G_EXP) return c * __builtin_amdgcn_exp2f(y * cl2);
   return 1.0f;
 }
 
@@ -113,18 +124,25 @@ __device__ __forceinline__ void ascend_all(float (&S)[1 << LP], const float *__r
 }
 
 // Sum over the 64 lanes of each of 64 per-lane values: afterwards v[0] of
-// lane l holds sum over lanes of v[l] (butterfly transpose-reduction).
-__device__ __forceinline__ float transpose_reduce64(float (&v)[64], int lane) {
+// lane l holds sum over lanes of v[l] (butterfly transpose-reduction: at
+// distance D a lane keeps the half of its slots selected by bit D of its
+// lane id and adds the partner's copy of those slots).
+template <int D>
+__device__ __forceinline__ void transpose_step(float (&v)[64], int lane) {
+  if constexpr (D >= 1) {
+    const bool hi = (lane & D) != 0;
 #pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) {
-    const bool hi = (lane & d) != 0;
-#pragma unroll
-    for (int c = 0; c < d; ++c) {
-      const float send = hi ? v[c] : v[c + d];
-      const float keep = hi ? v[c + d] : v[c];
-      v[c] = keep + __shfl_xor(send, d, 64);
+    for (int c = 0; c < D; ++c) {
+      const float send = hi ? v[c] : v[c + D];
+      const float keep = hi ? v[c + D] : v[c];
+      v[c] = keep + __shfl_xor(send, D, 64);
     }
+    transpose_step<D / 2>(v, lane);
   }
+}
+
+__device__ __forceinline__ float transpose_reduce64(float (&v)[64], int lane) {
+  transpose_step<32>(v, lane);
   return v[0];
 }
 
@@ -190,12 +208,12 @@ __global__ __launch_bounds__(256) void leaf_kernel(LeafArgs a, const float *__re
     if (MODE == kModeSum) {
       float s = 0.f;
 #pragma unroll
-      for (int c = 0; c < NL; ++c) s += g_val<GF>(y[c], a.gc);
+      for (int c = 0; c < NL; ++c) s += g_val<GF>(y[c], a.gcl2);
       if (live) acc += (double)s;
     } else if (MODE == kModePoint) {
       float v[64];
 #pragma unroll
-      for (int c = 0; c < 64; ++c) v[c] = (c < NL && live) ? g_val<GF>(y[c < NL ? c : 0], a.gc) : 0.f;
+      for (int c = 0; c < 64; ++c) v[c] = (c < NL && live) ? g_val<GF>(y[c < NL ? c : 0], a.gcl2) : 0.f;
       const float tot = transpose_reduce64(v, lane);
       if (lane < NL) ppart[(((int64_t)rl * a.tct + ct) * G.nsub + rho) * NL + lane] = tot;
     } else if (MODE == kModeStoreY) {
@@ -209,9 +227,9 @@ __global__ __launch_bounds__(256) void leaf_kernel(LeafArgs a, const float *__re
       const float *hk = hd ? hd + ((int64_t)rl * G.nsub + rho) * NL : nullptr;
 #pragma unroll
       for (int c = 0; c < NL; ++c) {
-        if (hd == nullptr) s += g_val<GF>(y[c], a.gc);
+        if (hd == nullptr) s += g_val<GF>(y[c], a.gcl2);
         const float fac = hk ? hk[c] : 1.0f;
-        S[c] = live ? (float)(a.gscale * (double)(fac * g_der<GF>(y[c], a.gc))) : 0.f;
+        S[c] = live ? (float)(a.gscale * (double)(fac * g_der<GF>(y[c], a.gcl2, a.gc))) : 0.f;
       }
       if (live && hd == nullptr) acc += (double)s;
       ascend_all<LP, 0>(S, rec, G, dAl, lane);
@@ -298,6 +316,7 @@ hipError_t launch_leaf(const Geometry &G, int mode, const qmc_integrand &f, cons
   a.ldu = ldu;
   a.ldy = o.ldy;
   a.gc = (float)f.c;
+  a.gcl2 = (float)(f.c * 1.4426950408889634074);
   a.gscale = o.gscale;
   dim3 grid(lp.gx, a.tct, nr);
   const size_t lds = sizeof(float) * (size_t)G.jlow * kTileT * (mode == kModeGrad ? 1 + lp.nw : 1);

@@ -10,6 +10,8 @@
 // Section 2.3) and the result is rounded once to FP32.  All integer work is
 // exact; the FP64 sequence is fixed (no contraction) so tables are
 // reproducible bit for bit.
+#include <algorithm>
+
 #include "qmc_internal.h"
 
 #pragma clang fp contract(off)
@@ -36,6 +38,7 @@ __device__ __forceinline__ uint32_t value_int(const Geometry &G, const uint32_t 
   return __builtin_bitreverse32(y) >> (32 - nb);
 }
 
+template <bool INVNORM>
 __device__ __forceinline__ double value_f64(const Geometry &G, const DevSpec &D, int r, int j,
                                             uint32_t rho, int nb) {
   const uint32_t c = value_int(G, D.gen, j, rho, nb);
@@ -50,66 +53,59 @@ __device__ __forceinline__ double value_f64(const Geometry &G, const DevSpec &D,
       if (x >= 1.0) x = __dsub_rn(x, 1.0);
     }
   }
+  if (INVNORM) return normcdfinv(x);
   switch (G.map) {
     case QMC_MAP_CENTER: return __dsub_rn(x, 0.5);
-    case QMC_MAP_INVNORM: return normcdfinv(x);
     case QMC_MAP_TENT: return __dsub_rn(1.0, fabs(__dsub_rn(1.0, __dmul_rn(2.0, x))));
     default: return x;
   }
 }
 
-// Map a table entry e (per shift) to (coordinate j, residue rho, nb).
-__device__ __forceinline__ void locate(const Geometry &G, int64_t e, int &j, uint32_t &rho, int &nb) {
-  if (e < G.lower_total) {
-    const int64_t sub = e / G.rec;
-    const int64_t o = e - sub * G.rec;
-    for (int I = G.split - 1; I >= 0; --I) {
-      const Level &L = G.lev[I];
-      const int64_t nc = int64_t(1) << (G.split - I);
-      if (L.tau > 0 && o >= L.off && o < L.off + L.tau * nc) {
-        const int64_t q = o - L.off;
-        j = L.j0 + (int)(q / nc);
-        rho = (uint32_t)(sub + (q % nc) * G.nsub);
-        nb = L.nb;
-        return;
-      }
+// One launch covers every level ("segment") and every shift: blockIdx.y is
+// the segment (lower levels L'-1..0, then the upper levels), blockIdx.z the
+// shift.  A segment holds tau_I * n_I values.
+//   lower level I: o -> (c = o mod 2^{L'-I}, jj, subtree root sub); the value
+//                  of coordinate j0 + jj at residue sub + c n_{L'} goes to
+//                  record sub, offset off_I + jj 2^{L'-I} + c
+//   upper level I: o -> (row = o / tau_I, jj = o mod tau_I), stored row-major
+template <bool INVNORM>
+__global__ __launch_bounds__(256) void tables_kernel(Geometry G, DevSpec D, int r0,
+                                                     float *__restrict__ out) {
+  const int seg = blockIdx.y, rl = blockIdx.z;
+  const bool lower = seg < G.split;
+  const int I = lower ? G.split - 1 - seg : G.up[seg - G.split];
+  const Level &L = G.lev[I];
+  const uint32_t tau = (uint32_t)L.tau;
+  const uint32_t count = tau << L.nb;
+  float *o_r = out + (int64_t)rl * G.table_total;
+  const int shiftc = G.split - I;  // log2 of the nodes per subtree at a lower level
+  for (uint32_t o = blockIdx.x * 256 + threadIdx.x; o < count; o += gridDim.x * 256) {
+    uint32_t rho, jj;
+    int64_t dst;
+    if (lower) {
+      const uint32_t c = o & ((1u << shiftc) - 1u);
+      const uint32_t qq = o >> shiftc;
+      jj = qq % tau;
+      const uint32_t sub = qq / tau;
+      rho = sub + (c << (G.m - G.split));
+      dst = (int64_t)sub * G.rec + L.off + ((int64_t)jj << shiftc) + c;
+    } else {
+      rho = o / tau;
+      jj = o - rho * tau;
+      dst = G.lower_total + L.off + o;
     }
-  } else {
-    const int64_t q = e - G.lower_total;
-    for (int u = 0; u < G.nup; ++u) {
-      const Level &L = G.lev[G.up[u]];
-      const int64_t n = int64_t(1) << L.nb;
-      if (q >= L.off && q < L.off + n * L.tau) {
-        const int64_t o = q - L.off;
-        rho = (uint32_t)(o / L.tau);
-        j = L.j0 + (int)(o % L.tau);
-        nb = L.nb;
-        return;
-      }
-    }
-  }
-  j = 0; rho = 0; nb = 0;  // unreachable for e < table_total
-}
-
-__global__ void tables_kernel(Geometry G, DevSpec D, int r0, int nr, float *__restrict__ out) {
-  const int64_t total = G.table_total * nr;
-  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    const int r = (int)(idx / G.table_total);
-    const int64_t e = idx - (int64_t)r * G.table_total;
-    int j, nb;
-    uint32_t rho;
-    locate(G, e, j, rho, nb);
-    out[idx] = (float)value_f64(G, D, r0 + r, j, rho, nb);
+    o_r[dst] = (float)value_f64<INVNORM>(G, D, r0 + rl, L.j0 + (int)jj, rho, L.nb);
   }
 }
 
+template <bool INVNORM>
 __global__ void values_kernel(Geometry G, DevSpec D, int r, int j, int nb, double *__restrict__ out) {
   const uint32_t n = 1u << nb;
   for (uint32_t rho = blockIdx.x * blockDim.x + threadIdx.x; rho < n; rho += gridDim.x * blockDim.x)
-    out[rho] = value_f64(G, D, r, j, rho, nb);
+    out[rho] = value_f64<INVNORM>(G, D, r, j, rho, nb);
 }
 
+template <bool INVNORM>
 __global__ void point_matrix_kernel(Geometry G, DevSpec D, int r, float *__restrict__ X, int64_t ldx) {
   const int64_t total = G.N * G.s;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
@@ -118,13 +114,13 @@ __global__ void point_matrix_kernel(Geometry G, DevSpec D, int r, float *__restr
     const int j = (int)(idx - k * G.s);
     const int nb = D.nbj[j];
     const uint32_t rho = (uint32_t)(k & ((int64_t(1) << nb) - 1));
-    X[k * ldx + j] = (float)value_f64(G, D, r, j, rho, nb);
+    X[k * ldx + j] = (float)value_f64<INVNORM>(G, D, r, j, rho, nb);
   }
 }
 
 static int grid_for(int64_t work, int threads) {
   int64_t g = ceil_div(work, threads);
-  if (g > 65536) g = 65536;
+  if (g > 65535) g = 65535;
   if (g < 1) g = 1;
   return (int)g;
 }
@@ -132,8 +128,14 @@ static int grid_for(int64_t work, int threads) {
 hipError_t launch_tables(const Geometry &G, const DevSpec &D, int r0, int nr, float *out,
                          hipStream_t st) {
   LaunchTimer tm("tables", st);
-  const int64_t work = G.table_total * nr;
-  hipLaunchKernelGGL(tables_kernel, dim3(grid_for(work, 256)), dim3(256), 0, st, G, D, r0, nr, out);
+  int64_t most = 1;
+  for (int I = 0; I <= G.m; ++I) most = std::max<int64_t>(most, (int64_t)G.lev[I].tau << G.lev[I].nb);
+  const int bx = std::min(grid_for(most, 256), 1024);
+  dim3 grid(bx, G.split + G.nup, nr);
+  if (G.map == QMC_MAP_INVNORM)
+    hipLaunchKernelGGL(tables_kernel<true>, grid, dim3(256), 0, st, G, D, r0, out);
+  else
+    hipLaunchKernelGGL(tables_kernel<false>, grid, dim3(256), 0, st, G, D, r0, out);
   return hipGetLastError();
 }
 
@@ -144,16 +146,22 @@ hipError_t launch_point_values(const Geometry &G, const DevSpec &D, int r, int j
   int nb = 0;
   for (int I = 0; I <= G.m; ++I)
     if (j >= G.lev[I].j0 && j < G.lev[I].j0 + G.lev[I].tau) nb = G.lev[I].nb;
-  hipLaunchKernelGGL(values_kernel, dim3(grid_for(int64_t(1) << nb, 256)), dim3(256), 0, st, G, D,
-                     r, j, nb, out);
+  const dim3 grid(grid_for(int64_t(1) << nb, 256));
+  if (G.map == QMC_MAP_INVNORM)
+    hipLaunchKernelGGL(values_kernel<true>, grid, dim3(256), 0, st, G, D, r, j, nb, out);
+  else
+    hipLaunchKernelGGL(values_kernel<false>, grid, dim3(256), 0, st, G, D, r, j, nb, out);
   return hipGetLastError();
 }
 
 hipError_t launch_point_matrix(const Geometry &G, const DevSpec &D, int r, float *X, int64_t ldx,
                                hipStream_t st) {
   LaunchTimer tm("points", st);
-  hipLaunchKernelGGL(point_matrix_kernel, dim3(grid_for(G.N * G.s, 256)), dim3(256), 0, st, G, D, r,
-                     X, ldx);
+  const dim3 grid(grid_for(G.N * G.s, 256));
+  if (G.map == QMC_MAP_INVNORM)
+    hipLaunchKernelGGL(point_matrix_kernel<true>, grid, dim3(256), 0, st, G, D, r, X, ldx);
+  else
+    hipLaunchKernelGGL(point_matrix_kernel<false>, grid, dim3(256), 0, st, G, D, r, X, ldx);
   return hipGetLastError();
 }
 
