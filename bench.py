@@ -55,6 +55,8 @@ def main() -> int:
     ap.add_argument("--prec", type=int, default=None, help="0 = FP32, 1 = split-BF16x3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dense", action="store_true")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="after timing, run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -170,6 +172,15 @@ def main() -> int:
                  "speedup_reduced_vs_dense": round(dms / ms, 2),
                  "rel_diff_vs_reduced": float(np.max(np.abs(Qd.cpu().numpy() - Qg) / np.abs(Qg)))}
         del X
+
+    if args.calibrate_copy_mib:
+        n = args.calibrate_copy_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     out = {
         "metric": "effective GFLOP/s (2*N*s*t*R/time), reduced QMC estimate vs dense X*A, rel err <= 1e-6",

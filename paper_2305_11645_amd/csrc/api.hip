@@ -1,4 +1,5 @@
 // C ABI of libqmcred: validation, level planning, workspace and launch order.
+#include <algorithm>
 #include <mutex>
 #include <string>
 #include <unordered_map>
@@ -154,7 +155,7 @@ size_t carve(const qmc::Geometry &G, int op, int t, const qmc_integrand *f, int 
   wk.U = c.take<float>((size_t)nr * G.urows * ldu);
   if (op == kOpMatvec) return c.used;
   const bool sep = f->h == QMC_H_ID;
-  wk.partial = c.take<double>((size_t)nr * (lp.gx > lg.gx ? lp.gx : lg.gx) * tct);
+  wk.partial = c.take<double>((size_t)nr * std::max(lp.gx * lp.gy, lg.gx * lg.gy));
   if (!sep) {
     wk.ppart = c.take<float>((size_t)nr * tct * G.N);
     wk.ppartial = c.take<double>((size_t)nr * point_h_blocks(G));
@@ -477,8 +478,8 @@ qmc_status qmc_reduced_matvec(qmc_points p, int32_t r, const float *A, int32_t t
   carve(p->G, kOpMatvec, t, &fid, 1, base, wk);
   const int64_t ldu = round_up(t, kTileT);
   const Geometry &G = p->G;
-  QMC_HIP(launch_tables(G, p->D, r, 1, wk.tables, st), "tables launch");
-  QMC_HIP(launch_levels(G, prec, wk.tables, 1, A, t, lda, wk.U, ldu, st), "levels launch");
+  QMC_HIP(launch_tables(G, p->D, r, 1, wk.tables, nullptr, 0, st), "tables launch");
+  QMC_HIP(launch_levels(G, prec, wk.tables, 1, A, t, lda, wk.U, ldu, 1.0f, st), "levels launch");
   LeafOut o{};
   o.Y = Y;
   o.ldy = ldy;
@@ -514,14 +515,16 @@ static qmc_status estimate_impl(qmc_points p, const float *A, int32_t t, int64_t
   const bool sep = f->h == QMC_H_ID;
   const double inv_nt = 1.0 / ((double)G.N * (double)t);
 
-  QMC_HIP(launch_tables(G, p->D, 0, nr, wk.tables, st), "tables launch");
-  QMC_HIP(launch_levels(G, prec, wk.tables, nr, A, t, lda, wk.U, ldu, st), "levels launch");
+  QMC_HIP(launch_tables(G, p->D, 0, nr, wk.tables, nullptr, 0, st), "tables launch");
+  const int leaf_mode = !sep ? kModePoint : (grad ? kModeGrad : kModeSum);
+  QMC_HIP(launch_levels(G, prec, wk.tables, nr, A, t, lda, wk.U, ldu, g_scale(*f, leaf_mode), st),
+          "levels launch");
   LeafOut o{};
   if (sep) {
     if (!grad) {
       o.partial = wk.partial;
       QMC_HIP(launch_leaf(G, kModeSum, *f, wk.tables, wk.U, nr, 0, A, t, lda, ldu, lp, o, st), "leaf launch");
-      QMC_HIP(launch_reduce(wk.partial, nr, (int64_t)lp.gx * tct, inv_nt, Q, st), "reduce launch");
+      QMC_HIP(launch_reduce(wk.partial, nr, (int64_t)lp.gx * lp.gy, inv_nt, Q, st), "reduce launch");
       return QMC_OK;
     }
   } else {
@@ -543,7 +546,7 @@ static qmc_status estimate_impl(qmc_points p, const float *A, int32_t t, int64_t
   g.hd = sep ? nullptr : wk.hd;
   g.gscale = inv_nt;
   QMC_HIP(launch_leaf(G, kModeGrad, *f, wk.tables, wk.U, nr, 0, A, t, lda, ldu, lg, g, st), "adjoint leaf launch");
-  if (sep) QMC_HIP(launch_reduce(wk.partial, nr, (int64_t)lg.gx * tct, inv_nt, Q, st), "reduce launch");
+  if (sep) QMC_HIP(launch_reduce(wk.partial, nr, (int64_t)lg.gx * lg.gy, inv_nt, Q, st), "reduce launch");
   QMC_HIP(launch_fold(G, nr, wk.S, t, ldu, st), "fold launch");
   QMC_HIP(launch_levels_adj(G, prec, wk.tables, nr, wk.S, t, ldu, wk.dup, st), "adjoint levels launch");
   QMC_HIP(launch_combine(G, wk.dlow, lg.gx, tct, wk.dup, nr, t, ldu, dA, st), "combine launch");

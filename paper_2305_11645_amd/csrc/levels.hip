@@ -42,6 +42,7 @@ struct GemmProb {
 
 struct GemmArgs {
   int32_t nprob, total_tiles;
+  float oscale;               // C = oscale * A B
   int64_t a_rs, b_rs, c_rs;   // per-shift strides of the three bases
   int64_t ldb, ldc;
   GemmProb p[kMaxLevels];
@@ -130,7 +131,7 @@ __global__ __launch_bounds__(256) void levels_gemm(GemmArgs g, const float *__re
     if (row < P.M && col < P.N) {
       float out = acc[v];
       if (PREC != QMC_FP32) out += acc2[v];
-      Cb[(int64_t)row * g.ldc + col] = out;
+      Cb[(int64_t)row * g.ldc + col] = g.oscale * out;
     }
   }
 }
@@ -148,9 +149,10 @@ static hipError_t run_gemm(const GemmArgs &a, int prec, int nr, const float *A, 
 }
 
 hipError_t launch_levels(const Geometry &G, int prec, const float *tables, int nr, const float *A,
-                         int t, int64_t lda, float *U, int64_t ldu, hipStream_t st) {
+                         int t, int64_t lda, float *U, int64_t ldu, float oscale, hipStream_t st) {
   LaunchTimer tm("levels", st);
   GemmArgs a = {};
+  a.oscale = oscale;
   a.a_rs = G.table_total;
   a.b_rs = 0;
   a.c_rs = G.urows * ldu;
@@ -199,6 +201,7 @@ hipError_t launch_levels_adj(const Geometry &G, int prec, const float *tables, i
                              const float *S, int t, int64_t ldu, float *part, hipStream_t st) {
   LaunchTimer tm("levels_adj", st);
   GemmArgs a = {};
+  a.oscale = 1.0f;
   a.a_rs = G.table_total;
   a.b_rs = (2 * G.nsub) * ldu;  // S pyramid rows per shift
   a.c_rs = levels_adj_part_floats(G, t, ldu);

@@ -82,8 +82,9 @@ inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
 // Each returns hipSuccess or the launch error.
 
 // Point tables (FP32) for shifts [r0, r0 + nr): out[(r - r0) * table_total + e].
+// Also zeroes counters[0..ncounters) (may be null) for the kernels that follow.
 hipError_t launch_tables(const Geometry &G, const DevSpec &D, int r0, int nr, float *out,
-                         hipStream_t st);
+                         uint32_t *counters, int ncounters, hipStream_t st);
 // Distinct FP64 values of coordinate j for shift r.
 hipError_t launch_point_values(const Geometry &G, const DevSpec &D, int r, int j, double *out,
                                hipStream_t st);
@@ -91,9 +92,9 @@ hipError_t launch_point_values(const Geometry &G, const DevSpec &D, int r, int j
 hipError_t launch_point_matrix(const Geometry &G, const DevSpec &D, int r, float *X, int64_t ldx,
                                hipStream_t st);
 
-// Grouped upper-level products U_I = X~_I A_I for shifts [0, nr) of the table buffer.
+// Grouped upper-level products U_I = oscale X~_I A_I for shifts [0, nr) of the table buffer.
 hipError_t launch_levels(const Geometry &G, int prec, const float *tables, int nr, const float *A,
-                         int t, int64_t lda, float *U, int64_t ldu, hipStream_t st);
+                         int t, int64_t lda, float *U, int64_t ldu, float oscale, hipStream_t st);
 
 // Adjoint of the upper levels: dA_I = X~_I^T S_I; S pyramid rows as in fold.
 hipError_t launch_levels_adj(const Geometry &G, int prec, const float *tables, int nr,
@@ -104,6 +105,26 @@ int64_t levels_adj_part_floats(const Geometry &G, int t, int64_t ldu);
 hipError_t launch_fold(const Geometry &G, int nr, float *S, int t, int64_t ldu, hipStream_t st);
 
 enum LeafMode { kModeSum = 0, kModePoint = 1, kModeStoreY = 2, kModeGrad = 3 };
+
+// Compact per-launch description of the lower levels for the leaf kernel.
+struct LeafLevel {
+  int32_t tau, off, j0, pad;   // coordinates, record offset (floats), first coordinate
+};
+
+struct LeafArgs {
+  int32_t t, tct, nsub, rec, spw, gx, gy, nw, cw, sw, jlow, r0, nup, nparts;
+  float xmax;                   // bound on |x| of every point value
+  int32_t up_row0[kMaxLevels];  // first U row of each upper level (per shift)
+  int32_t up_mask[kMaxLevels];  // n_I - 1
+  LeafLevel lv[kMaxSplit];
+  int64_t tstride, ustride, lda, ldu, ldy;
+  float sigma;                  // y' = sigma y: 1/(2 pi) for cos, c log2(e) for exp
+  float gc;                     // parameter c of exp(c y)
+  double gscale;                // adjoint factor
+};
+
+// sigma for an integrand and leaf mode
+float g_scale(const qmc_integrand &f, int mode);
 
 struct LeafOut {
   double *partial;     // kModeSum / kModeGrad: [nr][gx][tct] FP64 sums of g
@@ -118,8 +139,10 @@ struct LeafOut {
 
 struct LeafPlan {
   int gx;              // workgroups along the subtree axis
+  int gy;              // workgroups along the column-tile axis
   int spw;             // subtrees per wave
-  int nw;              // waves per workgroup
+  int nw;              // waves per workgroup = cw x sw
+  int cw, sw;          // column tiles x subtree groups per workgroup
 };
 LeafPlan leaf_plan(const Geometry &G, int t, int nr, int mode);
 

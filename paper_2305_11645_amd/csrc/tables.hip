@@ -68,10 +68,25 @@ __device__ __forceinline__ double value_f64(const Geometry &G, const DevSpec &D,
 //                  of coordinate j0 + jj at residue sub + c n_{L'} goes to
 //                  record sub, offset off_I + jj 2^{L'-I} + c
 //   upper level I: o -> (row = o / tau_I, jj = o mod tau_I), stored row-major
+// Flattened grid: block b belongs to (shift, segment) through the prefix sums
+// of per-segment block counts.
+struct TableGrid {
+  int32_t nseg;
+  int32_t blk0[kMaxLevels + 1];  // first block of each segment (per shift); blk0[nseg] = total
+};
+
 template <bool INVNORM>
-__global__ __launch_bounds__(256) void tables_kernel(Geometry G, DevSpec D, int r0,
-                                                     float *__restrict__ out) {
-  const int seg = blockIdx.y, rl = blockIdx.z;
+__global__ __launch_bounds__(256) void tables_kernel(Geometry G, DevSpec D, TableGrid tg, int r0,
+                                                     float *__restrict__ out,
+                                                     uint32_t *__restrict__ counters, int ncounters) {
+  if (blockIdx.x == 0 && blockIdx.y == 0)
+    for (int i = threadIdx.x; i < ncounters; i += blockDim.x) counters[i] = 0u;
+  const int rl = blockIdx.y;
+  int seg = 0;
+  for (int q = 1; q < tg.nseg; ++q)
+    if ((int)blockIdx.x >= tg.blk0[q]) seg = q;
+  const uint32_t b0 = blockIdx.x - tg.blk0[seg];
+  const uint32_t nb_seg = tg.blk0[seg + 1] - tg.blk0[seg];
   const bool lower = seg < G.split;
   const int I = lower ? G.split - 1 - seg : G.up[seg - G.split];
   const Level &L = G.lev[I];
@@ -79,7 +94,7 @@ __global__ __launch_bounds__(256) void tables_kernel(Geometry G, DevSpec D, int 
   const uint32_t count = tau << L.nb;
   float *o_r = out + (int64_t)rl * G.table_total;
   const int shiftc = G.split - I;  // log2 of the nodes per subtree at a lower level
-  for (uint32_t o = blockIdx.x * 256 + threadIdx.x; o < count; o += gridDim.x * 256) {
+  for (uint32_t o = b0 * 256 + threadIdx.x; o < count; o += nb_seg * 256) {
     uint32_t rho, jj;
     int64_t dst;
     if (lower) {
@@ -126,16 +141,24 @@ static int grid_for(int64_t work, int threads) {
 }
 
 hipError_t launch_tables(const Geometry &G, const DevSpec &D, int r0, int nr, float *out,
-                         hipStream_t st) {
+                         uint32_t *counters, int ncounters, hipStream_t st) {
   LaunchTimer tm("tables", st);
-  int64_t most = 1;
-  for (int I = 0; I <= G.m; ++I) most = std::max<int64_t>(most, (int64_t)G.lev[I].tau << G.lev[I].nb);
-  const int bx = std::min(grid_for(most, 256), 1024);
-  dim3 grid(bx, G.split + G.nup, nr);
+  TableGrid tg{};
+  tg.nseg = G.split + G.nup;
+  int total = 0;
+  for (int q = 0; q < tg.nseg; ++q) {
+    const int I = q < G.split ? G.split - 1 - q : G.up[q - G.split];
+    const int64_t count = (int64_t)G.lev[I].tau << G.lev[I].nb;
+    tg.blk0[q] = total;
+    total += (int)std::min<int64_t>(ceil_div(count, 256), 512);
+  }
+  tg.blk0[tg.nseg] = total;
+  if (total == 0) total = 1;  // still zero the counters
+  dim3 grid(total, nr);
   if (G.map == QMC_MAP_INVNORM)
-    hipLaunchKernelGGL(tables_kernel<true>, grid, dim3(256), 0, st, G, D, r0, out);
+    hipLaunchKernelGGL(tables_kernel<true>, grid, dim3(256), 0, st, G, D, tg, r0, out, counters, ncounters);
   else
-    hipLaunchKernelGGL(tables_kernel<false>, grid, dim3(256), 0, st, G, D, r0, out);
+    hipLaunchKernelGGL(tables_kernel<false>, grid, dim3(256), 0, st, G, D, tg, r0, out, counters, ncounters);
   return hipGetLastError();
 }
 
