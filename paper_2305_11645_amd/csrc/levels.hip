@@ -27,9 +27,10 @@ namespace qmc {
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-constexpr int BM = 64, BN = 64, BK = 16;
+constexpr int BM = 64, BN = 64, BK = 32;
 constexpr int APAD = BK + 1;   // As row stride (odd: conflict-free column reads)
 constexpr int BPAD = BN + 4;
+constexpr int PER_T = BM * BK / 256;  // elements of each operand tile per thread (8)
 
 struct GemmProb {
   int32_t M, N, K;
@@ -47,6 +48,33 @@ struct GemmArgs {
   int64_t ldb, ldc;
   GemmProb p[kMaxLevels];
 };
+
+// Operand tile coordinates of element q of this thread: A as (i, k), B as (k, j).
+template <bool TA>
+__device__ __forceinline__ void a_coord(int e, int &i, int &k) {
+  if (TA) { k = e / BM; i = e % BM; } else { i = e / BK; k = e % BK; }
+}
+
+// Loads the A and B tiles at K offset k0.  Ab and Bb already point at this
+// thread's first element (row i0 + i, column k of A; row k, column j0 + j of B);
+// element q of the thread lies q * (256 / BK) rows further for A (BK/256 * q for
+// TA) and q * (256 / BN) rows further for B.
+template <bool TA>
+__device__ __forceinline__ void load_tile(const float *__restrict__ Ab, const float *__restrict__ Bb,
+                                          int64_t a_step, int64_t b_step, int a_rows_left,
+                                          int b_k0, int k0, int kend, bool a_col_ok, bool b_col_ok,
+                                          int a_k, float (&ra)[PER_T], float (&rb)[PER_T]) {
+#pragma unroll
+  for (int q = 0; q < PER_T; ++q) {
+    // A element q: TA: k advances by 256/BM per q; else the row advances by 256/BK
+    bool aok;
+    if (TA) aok = a_col_ok && (k0 + a_k + q * (256 / BM)) < kend;
+    else aok = (q * (256 / BK)) < a_rows_left && (k0 + a_k) < kend;
+    ra[q] = aok ? Ab[q * a_step] : 0.f;
+    const bool bok = b_col_ok && (k0 + b_k0 + q * (256 / BN)) < kend;
+    rb[q] = bok ? Bb[q * b_step] : 0.f;
+  }
+}
 
 template <bool TA, int PREC>
 __global__ __launch_bounds__(256) void levels_gemm(GemmArgs g, const float *__restrict__ Abase,
@@ -76,25 +104,40 @@ __global__ __launch_bounds__(256) void levels_gemm(GemmArgs g, const float *__re
 
   f32x16 acc = {0};
   f32x16 acc2 = {0};
+  // this thread's element 0 of each operand tile
+  int ai, ak;
+  a_coord<TA>(tid, ai, ak);
+  const int bk = tid / BN, bj = tid % BN;
+  const bool a_col_ok = TA ? (i0 + ai) < P.M : true;
+  const int a_rows_left = TA ? 0 : P.M - (i0 + ai);
+  const bool b_col_ok = (j0 + bj) < P.N;
+  // per-q steps: A rows (or k) and B rows advance with q
+  const int64_t a_step = TA ? (int64_t)(256 / BM) * P.a_sk : (int64_t)(256 / BK) * P.a_si;
+  const int64_t b_step = (int64_t)(256 / BN) * g.ldb;
+  const float *Ap = Ab + (int64_t)(i0 + ai) * P.a_si + (int64_t)(kbeg + ak) * P.a_sk;
+  const float *Bp = Bb + (int64_t)(kbeg + bk) * g.ldb + (j0 + bj);
+  const int64_t a_kstep = (int64_t)BK * P.a_sk, b_kstep = (int64_t)BK * g.ldb;
+  float ra[PER_T], rb[PER_T];
+  load_tile<TA>(Ap, Bp, a_step, b_step, a_rows_left, bk, kbeg, kend, a_col_ok, b_col_ok, ak, ra, rb);
 
   for (int k0 = kbeg; k0 < kend; k0 += BK) {
-    // stage A (BM x BK) and B (BK x BN), zero outside the problem
+    __syncthreads();  // the previous tile has been consumed
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < PER_T; ++q) {
       const int e = tid + 256 * q;
       int i, k;
-      if (TA) { k = e / BM; i = e % BM; } else { i = e / BK; k = e % BK; }
-      const int gi = i0 + i, gk = k0 + k;
-      float v = 0.f;
-      if (gi < P.M && gk < kend) v = Ab[gi * P.a_si + gk * P.a_sk];
-      As[i * APAD + k] = v;
-      const int kb = e / BN, jb = e % BN;
-      const int gkb = k0 + kb, gj = j0 + jb;
-      float u = 0.f;
-      if (gkb < kend && gj < P.N) u = Bb[(int64_t)gkb * g.ldb + gj];
-      Bs[kb * BPAD + jb] = u;
+      a_coord<TA>(e, i, k);
+      As[i * APAD + k] = ra[q];
+      Bs[(e / BN) * BPAD + (e % BN)] = rb[q];
     }
     __syncthreads();
+    // the next tile's loads are in flight while this one is multiplied
+    if (k0 + BK < kend) {
+      Ap += a_kstep;
+      Bp += b_kstep;
+      load_tile<TA>(Ap, Bp, a_step, b_step, a_rows_left, bk, k0 + BK, kend, a_col_ok, b_col_ok, ak,
+                    ra, rb);
+    }
     if (PREC == QMC_FP32) {
 #pragma unroll
       for (int kk = 0; kk < BK; kk += 2) {
@@ -103,24 +146,26 @@ __global__ __launch_bounds__(256) void levels_gemm(GemmArgs g, const float *__re
         acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
       }
     } else {
-      bf16x8 ah, al, bh, bl;
-      const int kq = 8 * (lane >> 5);
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const float a = As[(wr + (lane & 31)) * APAD + kq + q];
-        const __bf16 a_hi = (__bf16)a;
-        ah[q] = a_hi;
-        al[q] = (__bf16)(a - (float)a_hi);
-        const float b = Bs[(kq + q) * BPAD + wc + (lane & 31)];
-        const __bf16 b_hi = (__bf16)b;
-        bh[q] = b_hi;
-        bl[q] = (__bf16)(b - (float)b_hi);
+      for (int kc = 0; kc < BK; kc += 16) {
+        bf16x8 ah, al, bh, bl;
+        const int kq = kc + 8 * (lane >> 5);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const float a = As[(wr + (lane & 31)) * APAD + kq + q];
+          const __bf16 a_hi = (__bf16)a;
+          ah[q] = a_hi;
+          al[q] = (__bf16)(a - (float)a_hi);
+          const float b = Bs[(kq + q) * BPAD + wc + (lane & 31)];
+          const __bf16 b_hi = (__bf16)b;
+          bh[q] = b_hi;
+          bl[q] = (__bf16)(b - (float)b_hi);
+        }
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc, 0, 0, 0);
+        acc2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc2, 0, 0, 0);
+        acc2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc2, 0, 0, 0);
       }
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc, 0, 0, 0);
-      acc2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc2, 0, 0, 0);
-      acc2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc2, 0, 0, 0);
     }
-    __syncthreads();
   }
 
   float *Cb = Cbase + r * g.c_rs + P.c_off + (int64_t)chunk * P.c_chunk;
@@ -184,7 +229,8 @@ hipError_t launch_levels(const Geometry &G, int prec, const float *tables, int n
 
 // Adjoint partial layout: for each upper level (in order) kchunks blocks of
 // tau_I x ldu floats, per shift.
-static int adj_chunk(int64_t K) { return (int)(K < 1024 ? round_up(K, BK) : 1024); }
+int64_t levels_adj_kchunk(int64_t K) { return K < 1024 ? round_up(K, BK) : 1024; }
+static int adj_chunk(int64_t K) { return (int)levels_adj_kchunk(K); }
 
 int64_t levels_adj_part_floats(const Geometry &G, int t, int64_t ldu) {
   (void)t;

@@ -100,6 +100,8 @@ hipError_t launch_levels(const Geometry &G, int prec, const float *tables, int n
 hipError_t launch_levels_adj(const Geometry &G, int prec, const float *tables, int nr,
                              const float *S, int t, int64_t ldu, float *part, hipStream_t st);
 int64_t levels_adj_part_floats(const Geometry &G, int t, int64_t ldu);
+// K-chunk (rows of S per partial) of the adjoint level products
+int64_t levels_adj_kchunk(int64_t K);
 
 // Fold of the subtree-root sums over the upper levels (S_{I+1} from S_I).
 hipError_t launch_fold(const Geometry &G, int nr, float *S, int t, int64_t ldu, hipStream_t st);

@@ -47,7 +47,7 @@ hipError_t launch_reduce(const double *partial, int nr, int64_t per, double scal
   return hipGetLastError();
 }
 
-constexpr int kPointsPerBlock = 4096;
+constexpr int kPointsPerBlock = 1024;
 
 int64_t point_h_blocks(const Geometry &G) { return ceil_div(G.N, kPointsPerBlock); }
 
@@ -172,7 +172,7 @@ hipError_t launch_combine(const Geometry &G, const float *dApart_low, int gx, in
   for (int u = 0; u < G.nup; ++u) {
     const Level &L = G.lev[G.up[u]];
     const int64_t K = int64_t(1) << L.nb;
-    const int64_t kc = K < 1024 ? round_up(K, 16) : 1024;
+    const int64_t kc = levels_adj_kchunk(K);
     a.kchunks[u] = (int)ceil_div(K, kc);
     a.poff[u] = poff;
     poff += (int64_t)a.kchunks[u] * L.tau * ldu;

@@ -18,7 +18,14 @@
 
 namespace qmc {
 
-__device__ __forceinline__ uint32_t value_int(const Geometry &G, const uint32_t *__restrict__ gen,
+// The point-set constants the value computation needs.
+struct PointConsts {
+  int32_t m, s, kind, rand, map;
+};
+
+static PointConsts consts_of(const Geometry &G) { return PointConsts{G.m, G.s, G.kind, G.rand, G.map}; }
+
+__device__ __forceinline__ uint32_t value_int(const PointConsts &G, const uint32_t *__restrict__ gen,
                                               int j, uint32_t rho, int nb) {
   if (nb == 0) return 0u;
   const uint32_t mask = (nb >= 32) ? 0xffffffffu : ((1u << nb) - 1u);
@@ -38,8 +45,56 @@ __device__ __forceinline__ uint32_t value_int(const Geometry &G, const uint32_t 
   return __builtin_bitreverse32(y) >> (32 - nb);
 }
 
+// Inverse standard normal CDF in FP64: Wichura, "Algorithm AS 241: The
+// percentage points of the normal distribution", Applied Statistics 37
+// (1988), PPND16 -- rational approximations of degree 7 in three regions,
+// relative accuracy about 1e-16.  Evaluated with Horner's rule.
+__device__ __forceinline__ double ppnd16(double p) {
+  const double q = p - 0.5;
+  if (fabs(q) <= 0.425) {
+    const double r = 0.180625 - q * q;
+    const double num =
+        ((((((2.5090809287301226727e+3 * r + 3.3430575583588128105e+4) * r + 6.7265770927008700853e+4) * r +
+            4.5921953931549871457e+4) * r + 1.3731693765509461125e+4) * r + 1.9715909503065514427e+3) * r +
+         1.3314166789178437745e+2) * r + 3.3871328727963666080e0;
+    const double den =
+        ((((((5.2264952788528545610e+3 * r + 2.8729085735721942674e+4) * r + 3.9307895800092710610e+4) * r +
+            2.1213794301586595867e+4) * r + 5.3941960214247511077e+3) * r + 6.8718700749205790830e+2) * r +
+         4.2313330701600911252e+1) * r + 1.0;
+    return q * num / den;
+  }
+  double r = q < 0.0 ? p : 1.0 - p;
+  if (r <= 0.0) return q < 0.0 ? -HUGE_VAL : HUGE_VAL;
+  r = sqrt(-log(r));
+  double v;
+  if (r <= 5.0) {
+    r -= 1.6;
+    const double num =
+        ((((((7.74545014278341407640e-4 * r + 2.27238449892691845833e-2) * r + 2.41780725177450611770e-1) * r +
+            1.27045825245236838258e0) * r + 3.64784832476320460504e0) * r + 5.76949722146069140550e0) * r +
+         4.63033784615654529590e0) * r + 1.42343711074968357734e0;
+    const double den =
+        ((((((1.05075007164441684324e-9 * r + 5.47593808499534494600e-4) * r + 1.51986665636164571966e-2) * r +
+            1.48103976427480074590e-1) * r + 6.89767334985100004550e-1) * r + 1.67638483018380384940e0) * r +
+         2.05319162663775882187e0) * r + 1.0;
+    v = num / den;
+  } else {
+    r -= 5.0;
+    const double num =
+        ((((((2.01033439929228813265e-7 * r + 2.71155556874348757815e-5) * r + 1.24266094738807843860e-3) * r +
+            2.65321895265761230930e-2) * r + 2.96560571828504891230e-1) * r + 1.78482653991729133580e0) * r +
+         5.46378491116411436990e0) * r + 6.65790464350110377720e0;
+    const double den =
+        ((((((2.04426310338993978564e-15 * r + 1.42151175831644588870e-7) * r + 1.84631831751005468180e-5) * r +
+            7.86869131145613259100e-4) * r + 1.48753612908506148525e-2) * r + 1.36929880922735805310e-1) * r +
+         5.99832206555887937690e-1) * r + 1.0;
+    v = num / den;
+  }
+  return q < 0.0 ? -v : v;
+}
+
 template <bool INVNORM>
-__device__ __forceinline__ double value_f64(const Geometry &G, const DevSpec &D, int r, int j,
+__device__ __forceinline__ double value_f64(const PointConsts &G, const DevSpec &D, int r, int j,
                                             uint32_t rho, int nb) {
   const uint32_t c = value_int(G, D.gen, j, rho, nb);
   double x;
@@ -53,7 +108,7 @@ __device__ __forceinline__ double value_f64(const Geometry &G, const DevSpec &D,
       if (x >= 1.0) x = __dsub_rn(x, 1.0);
     }
   }
-  if (INVNORM) return normcdfinv(x);
+  if (INVNORM) return ppnd16(x);
   switch (G.map) {
     case QMC_MAP_CENTER: return __dsub_rn(x, 0.5);
     case QMC_MAP_TENT: return __dsub_rn(1.0, fabs(__dsub_rn(1.0, __dmul_rn(2.0, x))));
@@ -61,68 +116,88 @@ __device__ __forceinline__ double value_f64(const Geometry &G, const DevSpec &D,
   }
 }
 
-// One launch covers every level ("segment") and every shift: blockIdx.y is
-// the segment (lower levels L'-1..0, then the upper levels), blockIdx.z the
-// shift.  A segment holds tau_I * n_I values.
+// One launch covers every level ("segment") and every shift: blockIdx.x runs
+// over the blocks of all segments (lower levels L'-1..0, then the upper
+// levels), blockIdx.y is the shift.  A segment holds tau_I * n_I values.
 //   lower level I: o -> (c = o mod 2^{L'-I}, jj, subtree root sub); the value
 //                  of coordinate j0 + jj at residue sub + c n_{L'} goes to
 //                  record sub, offset off_I + jj 2^{L'-I} + c
 //   upper level I: o -> (row = o / tau_I, jj = o mod tau_I), stored row-major
-// Flattened grid: block b belongs to (shift, segment) through the prefix sums
-// of per-segment block counts.
-struct TableGrid {
-  int32_t nseg;
-  int32_t blk0[kMaxLevels + 1];  // first block of each segment (per shift); blk0[nseg] = total
+struct TabSeg {
+  int32_t blk0, nblk;   // blocks of this segment
+  int32_t lower, sh;    // lower level?  log2 of its nodes per subtree
+  uint32_t tau, count;  // coordinates, values
+  int32_t j0, nb;       // first coordinate, n_I = 2^nb
+  int64_t dst;          // first table entry of the segment
 };
 
+struct TabArgs {
+  int32_t nseg, nblk;
+  int32_t rec;          // floats per subtree record
+  int32_t sub_sh;       // log2 n_{L'}
+  int64_t table_total;
+  PointConsts G;
+  TabSeg seg[kMaxLevels];
+};
+
+constexpr int kValsPerThread = 8;
+
 template <bool INVNORM>
-__global__ __launch_bounds__(256) void tables_kernel(Geometry G, DevSpec D, TableGrid tg, int r0,
+__global__ __launch_bounds__(256) void tables_kernel(TabArgs ta, DevSpec D, int r0,
                                                      float *__restrict__ out,
                                                      uint32_t *__restrict__ counters, int ncounters) {
   if (blockIdx.x == 0 && blockIdx.y == 0)
     for (int i = threadIdx.x; i < ncounters; i += blockDim.x) counters[i] = 0u;
   const int rl = blockIdx.y;
-  int seg = 0;
-  for (int q = 1; q < tg.nseg; ++q)
-    if ((int)blockIdx.x >= tg.blk0[q]) seg = q;
-  const uint32_t b0 = blockIdx.x - tg.blk0[seg];
-  const uint32_t nb_seg = tg.blk0[seg + 1] - tg.blk0[seg];
-  const bool lower = seg < G.split;
-  const int I = lower ? G.split - 1 - seg : G.up[seg - G.split];
-  const Level &L = G.lev[I];
-  const uint32_t tau = (uint32_t)L.tau;
-  const uint32_t count = tau << L.nb;
-  float *o_r = out + (int64_t)rl * G.table_total;
-  const int shiftc = G.split - I;  // log2 of the nodes per subtree at a lower level
-  for (uint32_t o = b0 * 256 + threadIdx.x; o < count; o += nb_seg * 256) {
-    uint32_t rho, jj;
-    int64_t dst;
-    if (lower) {
-      const uint32_t c = o & ((1u << shiftc) - 1u);
-      const uint32_t qq = o >> shiftc;
-      jj = qq % tau;
-      const uint32_t sub = qq / tau;
-      rho = sub + (c << (G.m - G.split));
-      dst = (int64_t)sub * G.rec + L.off + ((int64_t)jj << shiftc) + c;
-    } else {
-      rho = o / tau;
-      jj = o - rho * tau;
-      dst = G.lower_total + L.off + o;
+  int q = 0;
+#pragma unroll 1
+  for (int i = 1; i < ta.nseg; ++i)
+    if ((int)blockIdx.x >= ta.seg[i].blk0) q = i;
+  const TabSeg sg = ta.seg[q];
+  const uint32_t b0 = blockIdx.x - sg.blk0;
+  float *o_r = out + (int64_t)rl * ta.table_total + sg.dst;
+  const uint32_t step = sg.nblk * 256u * kValsPerThread;
+  for (uint32_t base = b0 * 256u * kValsPerThread + threadIdx.x; base < sg.count; base += step) {
+    // all index math and gathers first, then the arithmetic: the loads overlap
+    uint32_t rho[kValsPerThread], jv[kValsPerThread], dst[kValsPerThread];
+#pragma unroll
+    for (int v = 0; v < kValsPerThread; ++v) {
+      const uint32_t o = min(base + 256u * v, sg.count - 1);
+      uint32_t jj;
+      if (sg.lower) {
+        const uint32_t c = o & ((1u << sg.sh) - 1u);
+        const uint32_t qq = o >> sg.sh;
+        jj = qq % sg.tau;
+        const uint32_t sub = qq / sg.tau;
+        rho[v] = sub + (c << ta.sub_sh);
+        dst[v] = sub * (uint32_t)ta.rec + (jj << sg.sh) + c;
+      } else {
+        rho[v] = o / sg.tau;
+        jj = o - rho[v] * sg.tau;
+        dst[v] = o;
+      }
+      jv[v] = sg.j0 + jj;
     }
-    o_r[dst] = (float)value_f64<INVNORM>(G, D, r0 + rl, L.j0 + (int)jj, rho, L.nb);
+    float val[kValsPerThread];
+#pragma unroll
+    for (int v = 0; v < kValsPerThread; ++v)
+      val[v] = (float)value_f64<INVNORM>(ta.G, D, r0 + rl, (int)jv[v], rho[v], sg.nb);
+#pragma unroll
+    for (int v = 0; v < kValsPerThread; ++v)
+      if (base + 256u * v < sg.count) o_r[dst[v]] = val[v];
   }
 }
 
 template <bool INVNORM>
-__global__ void values_kernel(Geometry G, DevSpec D, int r, int j, int nb, double *__restrict__ out) {
+__global__ void values_kernel(PointConsts G, DevSpec D, int r, int j, int nb, double *__restrict__ out) {
   const uint32_t n = 1u << nb;
   for (uint32_t rho = blockIdx.x * blockDim.x + threadIdx.x; rho < n; rho += gridDim.x * blockDim.x)
     out[rho] = value_f64<INVNORM>(G, D, r, j, rho, nb);
 }
 
 template <bool INVNORM>
-__global__ void point_matrix_kernel(Geometry G, DevSpec D, int r, float *__restrict__ X, int64_t ldx) {
-  const int64_t total = G.N * G.s;
+__global__ void point_matrix_kernel(PointConsts G, DevSpec D, int r, float *__restrict__ X, int64_t ldx) {
+  const int64_t total = ((int64_t)1 << G.m) * G.s;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
        idx += (int64_t)gridDim.x * blockDim.x) {
     const int64_t k = idx / G.s;
@@ -143,22 +218,36 @@ static int grid_for(int64_t work, int threads) {
 hipError_t launch_tables(const Geometry &G, const DevSpec &D, int r0, int nr, float *out,
                          uint32_t *counters, int ncounters, hipStream_t st) {
   LaunchTimer tm("tables", st);
-  TableGrid tg{};
-  tg.nseg = G.split + G.nup;
+  TabArgs ta{};
+  ta.G = consts_of(G);
+  ta.nseg = G.split + G.nup;
+  ta.rec = (int)G.rec;
+  ta.sub_sh = G.m - G.split;
+  ta.table_total = G.table_total;
   int total = 0;
-  for (int q = 0; q < tg.nseg; ++q) {
-    const int I = q < G.split ? G.split - 1 - q : G.up[q - G.split];
-    const int64_t count = (int64_t)G.lev[I].tau << G.lev[I].nb;
-    tg.blk0[q] = total;
-    total += (int)std::min<int64_t>(ceil_div(count, 256), 512);
+  for (int q = 0; q < ta.nseg; ++q) {
+    const bool lower = q < G.split;
+    const int I = lower ? G.split - 1 - q : G.up[q - G.split];
+    const Level &L = G.lev[I];
+    TabSeg &sg = ta.seg[q];
+    sg.lower = lower;
+    sg.sh = lower ? G.split - I : 0;
+    sg.tau = (uint32_t)L.tau;
+    sg.count = (uint32_t)L.tau << L.nb;
+    sg.j0 = L.j0;
+    sg.nb = L.nb;
+    sg.dst = lower ? L.off : G.lower_total + L.off;
+    sg.blk0 = total;
+    sg.nblk = (int)std::min<int64_t>(ceil_div(sg.count, 256 * kValsPerThread), 512);
+    total += sg.nblk;
   }
-  tg.blk0[tg.nseg] = total;
+  ta.nblk = total;
   if (total == 0) total = 1;  // still zero the counters
   dim3 grid(total, nr);
   if (G.map == QMC_MAP_INVNORM)
-    hipLaunchKernelGGL(tables_kernel<true>, grid, dim3(256), 0, st, G, D, tg, r0, out, counters, ncounters);
+    hipLaunchKernelGGL(tables_kernel<true>, grid, dim3(256), 0, st, ta, D, r0, out, counters, ncounters);
   else
-    hipLaunchKernelGGL(tables_kernel<false>, grid, dim3(256), 0, st, G, D, tg, r0, out, counters, ncounters);
+    hipLaunchKernelGGL(tables_kernel<false>, grid, dim3(256), 0, st, ta, D, r0, out, counters, ncounters);
   return hipGetLastError();
 }
 
@@ -171,9 +260,9 @@ hipError_t launch_point_values(const Geometry &G, const DevSpec &D, int r, int j
     if (j >= G.lev[I].j0 && j < G.lev[I].j0 + G.lev[I].tau) nb = G.lev[I].nb;
   const dim3 grid(grid_for(int64_t(1) << nb, 256));
   if (G.map == QMC_MAP_INVNORM)
-    hipLaunchKernelGGL(values_kernel<true>, grid, dim3(256), 0, st, G, D, r, j, nb, out);
+    hipLaunchKernelGGL(values_kernel<true>, grid, dim3(256), 0, st, consts_of(G), D, r, j, nb, out);
   else
-    hipLaunchKernelGGL(values_kernel<false>, grid, dim3(256), 0, st, G, D, r, j, nb, out);
+    hipLaunchKernelGGL(values_kernel<false>, grid, dim3(256), 0, st, consts_of(G), D, r, j, nb, out);
   return hipGetLastError();
 }
 
@@ -182,9 +271,9 @@ hipError_t launch_point_matrix(const Geometry &G, const DevSpec &D, int r, float
   LaunchTimer tm("points", st);
   const dim3 grid(grid_for(G.N * G.s, 256));
   if (G.map == QMC_MAP_INVNORM)
-    hipLaunchKernelGGL(point_matrix_kernel<true>, grid, dim3(256), 0, st, G, D, r, X, ldx);
+    hipLaunchKernelGGL(point_matrix_kernel<true>, grid, dim3(256), 0, st, consts_of(G), D, r, X, ldx);
   else
-    hipLaunchKernelGGL(point_matrix_kernel<false>, grid, dim3(256), 0, st, G, D, r, X, ldx);
+    hipLaunchKernelGGL(point_matrix_kernel<false>, grid, dim3(256), 0, st, consts_of(G), D, r, X, ldx);
   return hipGetLastError();
 }
 
