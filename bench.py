@@ -25,19 +25,41 @@ sys.path.insert(0, ROOT)
 
 import numpy as np  # noqa: E402
 
-# MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz = 3.93e13 VALU lane-slots/s.
-# One FP32 FMA per slot = 2 flops -> 78.6 TFLOP/s without packed FP32 (which
-# this build does not emit); transcendentals (v_cos, v_exp) take 4 slots.
-VALU_SLOTS_PER_S = 256 * 64 * 2.4e9
+# MI355X FP32 vector peak 157.3 TFLOP/s = 256 CUs x 128 FP32 lanes x 2.4 GHz x
+# 2 flops: 7.86e13 FMA lane-slots/s.  A transcendental (v_cos, v_sin, v_exp)
+# issues at a quarter of that rate, i.e. costs 4 slots (measured on the GPU:
+# cos 16.8e12/s, 85% of the quarter rate).  Achieved = 2 x algorithmic slots /
+# duration, in FP32-FMA-equivalent TFLOP/s, against 157.3.
+VALU_SLOTS_PER_S = 256 * 128 * 2.4e9
 VALU_PEAK_TFLOPS = 2 * VALU_SLOTS_PER_S / 1e12
-G_SLOTS = {0: 0, 1: 5, 2: 5}  # per evaluation of g: id; cos = mul + v_cos; exp = mul + v_exp
+G_SLOTS = {0: 0, 1: 4, 2: 4}  # per evaluation of g: id; cos; exp (one transcendental)
+
+
+def leaf_traffic(config: int):
+    """HBM bytes per leaf-kernel launch from the committed counter summary of this
+    workload, or None when there is none or the kernel source changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"leaf_kernel_C{config}_counters.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for ln in open(path):
+        if ":" in ln and ln.startswith("    "):
+            k, v = ln.strip().split(":", 1)
+            fields[k.strip()] = v.strip()
+    csrc = os.path.join(ROOT, "paper_2305_11645_amd", "csrc")
+    sha = hashlib.sha256(open(os.path.join(csrc, "leaf.hip"), "rb").read()
+                         + open(os.path.join(csrc, "qmc_internal.h"), "rb").read()).hexdigest()[:16]
+    if fields.get("kernel_source_sha256_16") != sha or "hbm_bytes_per_dispatch" not in fields:
+        return None
+    return int(fields["hbm_bytes_per_dispatch"])
 
 
 def leaf_algorithmic_slots(wl, split: int) -> float:
-    """VALU lane operations the fused leaf pass must perform per launch (all shifts):
+    """VALU lane slots the fused leaf pass must spend per launch (all shifts):
     the lower-level multiply-adds t R sum_{j: min(w_j,m) < L'} n_j (Theorem 2's
     count on those coordinates), one add per subtree root and upper level, and
-    per point and column one g and one accumulation."""
+    per point and column one g (a transcendental: 4 slots) and one accumulation."""
     m, t, R, N = wl.m, wl.t, wl.R, wl.N
     lev = np.minimum(wl.w, m)
     nlow = sum(2 ** (m - int(I)) for I in lev if I < split)
@@ -114,7 +136,7 @@ def main() -> int:
     achieved = 2 * slots / (leaf_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "kernel": "leaf_kernel", "achieved": round(achieved, 3),
                 "peak": round(VALU_PEAK_TFLOPS, 1), "unit": "TFLOP/s",
-                "frac": round(achieved / VALU_PEAK_TFLOPS, 4), "traffic": None,
+                "frac": round(achieved / VALU_PEAK_TFLOPS, 4), "traffic": leaf_traffic(args.config),
                 "avg_ms": round(leaf_ms, 5), "algorithmic_lane_ops": slots}
 
     # accuracy gate and CPU baseline: the FP64 oracle
