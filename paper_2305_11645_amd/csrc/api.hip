@@ -151,7 +151,7 @@ size_t carve(const qmc::Geometry &G, int op, int t, const qmc_integrand *f, int 
   const LeafPlan lp = leaf_plan(G, t, nr, kModeSum);
   const LeafPlan lg = leaf_plan(G, t, nr, kModeGrad);
   wk = Work{};
-  wk.tables = c.take<float>((size_t)nr * G.table_total);
+  wk.tables = c.take<float>((size_t)nr * G.table_total + kTablePad);
   wk.U = c.take<float>((size_t)nr * G.urows * ldu);
   if (op == kOpMatvec) return c.used;
   const bool sep = f->h == QMC_H_ID;

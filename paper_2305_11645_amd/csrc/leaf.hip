@@ -33,6 +33,9 @@
 
 namespace qmc {
 
+constexpr int kRootBatch = 8;  // upper-level rows of a subtree root loaded together (summing mode)
+static_assert(kMaxUpPadded % kRootBatch == 0, "root batches must tile the padded level arrays");
+
 // cos and sin take the angle in revolutions on v_cos / v_sin; v_fract reduces
 // it exactly.  exp(c y) = 2^(y'), y' = c log2(e) y, on v_exp.
 template <int GF>
@@ -57,7 +60,146 @@ __device__ __forceinline__ float g_der(float ys, float c) {
   return 1.0f;
 }
 
-// One level of the descent: y[0 .. 2^{LP-L}) becomes the level-L node values.
+// Summing mode, lean form.  Only the per-level counts tau_I travel with the
+// kernel (one byte per level); the record offset and the first row of A of a
+// level follow from the counts while descending, so few scalar registers stay
+// live.  The point values of up to kBatchFloats nodes x coordinates and their
+// rows of A are requested together, then consumed: one memory round trip per
+// batch instead of one per coordinate.  The scalar loads may read up to 31
+// floats past a level's block (the point tables carry padding at their end);
+// the LDS reads of A up to 7 rows past a level's rows (kLdsPadRows zero rows
+// follow the staged rows).
+constexpr int kBatchFloats = 32;
+
+template <int NC>
+constexpr int batch_coords() {
+  return NC >= kBatchFloats ? 1 : (kBatchFloats / NC < 8 ? kBatchFloats / NC : 8);
+}
+
+// y[c] += x[c] a for c < NC, reading x in chunks of at most kBatchFloats.
+template <int NC>
+__device__ __forceinline__ void axpy_chunks(float *y, const float *__restrict__ x, float a) {
+  constexpr int CH = NC < kBatchFloats ? NC : kBatchFloats;
+#pragma unroll
+  for (int h = 0; h < NC / CH; ++h) {
+    float xs[CH];
+#pragma unroll
+    for (int i = 0; i < CH; ++i) xs[i] = x[h * CH + i];
+#pragma unroll
+    for (int i = 0; i < CH; ++i) asm volatile("" ::"s"(xs[i]));
+#pragma unroll
+    for (int i = 0; i < CH; ++i) y[h * CH + i] = fmaf(xs[i], a, y[h * CH + i]);
+  }
+}
+
+template <int LP, int L, int LAST>
+__device__ __forceinline__ void descend_lean(float (&y)[1 << LP], const float *__restrict__ rec,
+                                             int &xo, int &j0, uint64_t taus, const float *Al) {
+  if constexpr (L >= LAST) {
+    constexpr int NC = 1 << (LP - L);
+    constexpr int H = NC / 2;
+    constexpr int B = batch_coords<NC>();
+    const int tau = (int)((taus >> (8 * L)) & 0xff);
+    j0 -= tau;
+    if (tau == 0) {
+#pragma unroll
+      for (int c = 0; c < H; ++c) y[c + H] = y[c];
+    } else {
+      const float *x = rec + xo;
+      const float *Aj = Al + j0 * kTileT;  // row stride kTileT; kLdsPadRows zero rows follow
+      if constexpr (B * NC <= kBatchFloats) {
+        // first batch: coordinate 0 forms the children (the tile step)
+        float xs[B * NC], av[B];
+#pragma unroll
+        for (int i = 0; i < B * NC; ++i) xs[i] = x[i];
+#pragma unroll
+        for (int i = 0; i < B; ++i) av[i] = Aj[i * kTileT];
+        // consume every value here, so no load sinks into the guarded uses
+#pragma unroll
+        for (int i = 0; i < B * NC; ++i) asm volatile("" ::"s"(xs[i]));
+#pragma unroll
+        for (int i = 0; i < B; ++i) asm volatile("" ::"v"(av[i]));
+#pragma unroll
+        for (int c = 0; c < H; ++c) y[c + H] = fmaf(xs[c + H], av[0], y[c]);
+#pragma unroll
+        for (int c = 0; c < H; ++c) y[c] = fmaf(xs[c], av[0], y[c]);
+#pragma unroll
+        for (int i = 1; i < B; ++i) {
+          if (i >= tau) break;
+#pragma unroll
+          for (int c = 0; c < NC; ++c) y[c] = fmaf(xs[i * NC + c], av[i], y[c]);
+        }
+#pragma unroll 1
+        for (int jb = B; jb < tau; jb += B) {
+#pragma unroll
+          for (int i = 0; i < B * NC; ++i) xs[i] = x[jb * NC + i];
+#pragma unroll
+          for (int i = 0; i < B; ++i) av[i] = Aj[(jb + i) * kTileT];
+#pragma unroll
+          for (int i = 0; i < B * NC; ++i) asm volatile("" ::"s"(xs[i]));
+#pragma unroll
+          for (int i = 0; i < B; ++i) asm volatile("" ::"v"(av[i]));
+#pragma unroll
+          for (int i = 0; i < B; ++i) {
+            if (jb + i >= tau) break;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) y[c] = fmaf(xs[i * NC + c], av[i], y[c]);
+          }
+        }
+      } else {  // NC = 64 (level 0 with more than one coordinate): one at a time, in chunks
+        const float a0 = Aj[0];
+        float z[H];
+#pragma unroll
+        for (int c = 0; c < H; ++c) z[c] = y[c];
+        axpy_chunks<H>(y, x, a0);
+        axpy_chunks<H>(z, x + H, a0);
+#pragma unroll
+        for (int c = 0; c < H; ++c) y[c + H] = z[c];
+#pragma unroll 1
+        for (int jj = 1; jj < tau; ++jj) axpy_chunks<NC>(y, x + jj * NC, Aj[jj * kTileT]);
+      }
+      xo += tau * NC;
+    }
+    descend_lean<LP, L - 1, LAST>(y, rec, xo, j0, taus, Al);
+  }
+}
+
+// Level 0 with a single coordinate, fused with g: leaf c and c + H0 come from
+// the level-1 node c.  The 2 H0 point values are read in halves of at most
+// kBatchFloats.  Returns the FP32 sum of g over the subtree's leaves.
+template <int LP, int GF, bool NEAR>
+__device__ __forceinline__ float leaf_block(const float (&y)[1 << LP], const float *__restrict__ x0,
+                                            float a0) {
+  constexpr int H0 = (1 << LP) / 2;
+  constexpr int HB = H0 < kBatchFloats / 2 ? H0 : kBatchFloats / 2;
+  float s = 0.f;
+#pragma unroll
+  for (int h = 0; h < H0 / HB; ++h) {
+    float xa[HB], xb[HB];
+#pragma unroll
+    for (int i = 0; i < HB; ++i) {
+      xa[i] = x0[h * HB + i];
+      xb[i] = x0[H0 + h * HB + i];
+    }
+#pragma unroll
+    for (int i = 0; i < HB; ++i) asm volatile("" ::"s"(xa[i]), "s"(xb[i]));
+#pragma unroll
+    for (int i = 0; i < HB; ++i) {
+      const int c = h * HB + i;
+      if (NEAR) {
+        s += g_val_near<GF>(fmaf(xa[i], a0, y[c]));
+        s += g_val_near<GF>(fmaf(xb[i], a0, y[c]));
+      } else {
+        s += g_val<GF>(fmaf(xa[i], a0, y[c]));
+        s += g_val<GF>(fmaf(xb[i], a0, y[c]));
+      }
+    }
+  }
+  return s;
+}
+
+// One level of the descent, one coordinate at a time (the modes that keep
+// per-point state): y[0 .. 2^{LP-L}) becomes the level-L node values.
 template <int LP, int L>
 __device__ __forceinline__ void descend(float (&y)[1 << LP], const float *__restrict__ rec,
                                         const LeafLevel &lv, const float *Alds, int lda_s, int lane) {
@@ -157,30 +299,27 @@ __global__ __launch_bounds__(256) void leaf_kernel(LeafArgs a, const float *__re
                                                    float *__restrict__ Sroot,
                                                    const float *__restrict__ hd) {
   constexpr int NL = 1 << LP;
-  constexpr int H0 = NL / 2;
   extern __shared__ float smem[];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-  // wave layout: cw column tiles x sw subtree groups per workgroup
-  const int wc = w % a.cw, ws = w / a.cw;
-  const int bx = blockIdx.x, by = blockIdx.y, rl = blockIdx.z;
-  const int ct = by * a.cw + wc;
+  // every wave of the workgroup works on column tile by, on its own subtrees
+  const int bx = blockIdx.x, ct = blockIdx.y, rl = blockIdx.z;
   const int col = ct * kTileT + lane;
   const bool live = col < a.t;
   const int jlow = a.jlow;
-  const int wcols = a.cw * kTileT;  // columns of A staged by this workgroup
 
+  // rows 0 .. jlow-1 of sigma A for the tile, then kLdsPadRows zero rows
   float *Alds = smem;
-  for (int e = tid; e < jlow * wcols; e += blockDim.x) {
-    const int jr = e / wcols, cl = by * wcols + (e % wcols);
-    Alds[e] = cl < a.t ? a.sigma * A[(int64_t)jr * a.lda + cl] : 0.f;
+  for (int e = tid; e < (jlow + kLdsPadRows) * kTileT; e += blockDim.x) {
+    const int jr = e / kTileT, cl = ct * kTileT + (e % kTileT);
+    Alds[e] = jr < jlow && cl < a.t ? a.sigma * A[(int64_t)jr * a.lda + cl] : 0.f;
   }
-  float *dAl = smem + jlow * wcols + w * jlow * kTileT;
+  float *dAl = smem + (jlow + kLdsPadRows) * kTileT + w * jlow * kTileT;
   if (MODE == kModeGrad)
     for (int e = lane; e < jlow * kTileT; e += 64) dAl[e] = 0.f;
   __syncthreads();
-  const float *Aw = Alds + wc * kTileT;  // this wave's columns; row stride wcols
+  const float *Al = Alds + lane;  // this lane's column; row stride kTileT
 
   // For cos: the subtree root is reduced to [0, 1) revolutions once; if the
   // lower levels add at most 250 revolutions in magnitude on every lane, the
@@ -188,7 +327,7 @@ __global__ __launch_bounds__(256) void leaf_kernel(LeafArgs a, const float *__re
   bool near = false;
   if (GF == QMC_G_COS) {
     float bound = 0.f;
-    for (int j = 0; j < jlow; ++j) bound += fabsf(Aw[j * wcols + lane]);
+    for (int j = 0; j < jlow; ++j) bound += fabsf(Al[j * kTileT]);
     near = __all(bound * a.xmax < 250.0f);
   }
 
@@ -196,52 +335,50 @@ __global__ __launch_bounds__(256) void leaf_kernel(LeafArgs a, const float *__re
   const float *Ub = U + (int64_t)rl * a.ustride;
   double acc = 0.0;
 
-  const int first = (bx * a.sw + ws) * a.spw;
+  const int first = (bx * a.nw + w) * a.spw;
   const int last = min(first + a.spw, a.nsub);
   for (int rho = first; rho < last; ++rho) {
     const float *rec = tab + (int64_t)rho * a.rec;
 
+    // subtree root: the upper levels' rows, requested RB at a time
+    constexpr int RB = MODE == kModeSum ? kRootBatch : 1;
     float root = 0.f;
 #pragma unroll 1
-    for (int u = 0; u < a.nup; ++u) {
-      const float *row = Ub + (int64_t)(a.up_row0[u] + (rho & a.up_mask[u])) * a.ldu;
-      root += row[col];
+    for (int u0 = 0; u0 < a.nup; u0 += RB) {
+      float rv[RB];
+#pragma unroll
+      for (int i = 0; i < RB; ++i)  // entries past nup are zero: they read row 0
+        rv[i] = Ub[(int64_t)(a.up_row0[u0 + i] + (rho & a.up_mask[u0 + i])) * a.ldu + col];
+#pragma unroll
+      for (int i = 0; i < RB; ++i) asm volatile("" ::"v"(rv[i]));
+#pragma unroll
+      for (int i = 0; i < RB; ++i)
+        if (u0 + i < a.nup) root += rv[i];
     }
     if (GF == QMC_G_COS) root = __builtin_amdgcn_fractf(root);
 
     float y[NL];
     y[0] = root;
-    if (FUSE0) {
-      descend_to<LP, LP - 1, 1>(y, rec, a.lv, Aw, wcols, lane);
-    } else {
-      descend_to<LP, LP - 1, 0>(y, rec, a.lv, Aw, wcols, lane);
-    }
-
     if (MODE == kModeSum) {
+      // the level counts are re-read per subtree (opaque to the compiler), so
+      // the per-level offsets are not hoisted into registers held for the
+      // whole loop
+      uint64_t taus = a.taus;
+      asm volatile("" : "+s"(taus));
+      int xo = 0, j0 = jlow;
       float s = 0.f;
-      if (FUSE0) {
-        const float *x0 = rec + a.lv[0].off;
-        const float a0 = Aw[a.lv[0].j0 * wcols + lane];
-        if (near) {
-#pragma unroll
-          for (int c = 0; c < H0; ++c) {
-            s += g_val_near<GF>(fmaf(x0[c], a0, y[c]));
-            s += g_val_near<GF>(fmaf(x0[c + H0], a0, y[c]));
-          }
-        } else {
-#pragma unroll
-          for (int c = 0; c < H0; ++c) {
-            s += g_val<GF>(fmaf(x0[c], a0, y[c]));
-            s += g_val<GF>(fmaf(x0[c + H0], a0, y[c]));
-          }
-        }
+      if constexpr (FUSE0) {
+        descend_lean<LP, LP - 1, 1>(y, rec, xo, j0, taus, Al);
+        const float a0 = Al[0];  // level 0 is row 0
+        s = near ? leaf_block<LP, GF, true>(y, rec + xo, a0) : leaf_block<LP, GF, false>(y, rec + xo, a0);
       } else {
+        descend_lean<LP, LP - 1, 0>(y, rec, xo, j0, taus, Al);
 #pragma unroll
         for (int c = 0; c < NL; ++c) s += g_val<GF>(y[c]);
       }
       if (live) acc += (double)s;
     } else {
-      if (FUSE0) descend<LP, 0>(y, rec, a.lv[0], Aw, wcols, lane);
+      descend_to<LP, LP - 1, 0>(y, rec, a.lv, Alds, kTileT, lane);
       if (MODE == kModePoint) {
         float v[64];
 #pragma unroll
@@ -278,21 +415,18 @@ __global__ __launch_bounds__(256) void leaf_kernel(LeafArgs a, const float *__re
     if (tid == 0) {
       double tot = red[0];
       for (int q = 1; q < a.nw; ++q) tot += red[q];
-      partial[(int64_t)rl * a.nparts + bx * a.gy + by] = tot;
+      partial[(int64_t)rl * a.nparts + bx * a.gy + ct] = tot;
     }
   }
   if (MODE == kModeGrad) {
     __syncthreads();
-    // per column tile of the workgroup: sum the waves of all subtree groups
-    const float *base = smem + jlow * wcols;
+    // sum the per-wave dA accumulators of the workgroup
+    const float *base = smem + (jlow + kLdsPadRows) * kTileT;
     const int64_t st = (int64_t)jlow * kTileT;
-    for (int e = tid; e < a.cw * jlow * kTileT; e += blockDim.x) {
-      const int q = e / (jlow * kTileT), o = e % (jlow * kTileT);
-      const int ctq = by * a.cw + q;
-      if (ctq >= a.tct) continue;
+    for (int e = tid; e < st; e += blockDim.x) {
       float v = 0.f;
-      for (int g = 0; g < a.sw; ++g) v += base[(g * a.cw + q) * st + o];
-      dApart[(((int64_t)rl * a.gx + bx) * a.tct + ctq) * st + o] = v;
+      for (int g = 0; g < a.nw; ++g) v += base[g * st + e];
+      dApart[(((int64_t)rl * a.gx + bx) * a.tct + ct) * st + e] = v;
     }
   }
 }
@@ -308,17 +442,9 @@ LeafPlan leaf_plan(const Geometry &G, int t, int nr, int mode) {
   }
   LeafPlan p;
   p.spw = spw;
-  p.nw = mode == kModeGrad ? 2 : 4;
-  p.cw = 1;  // waves side by side over column tiles (1: each wave its own subtrees)
-  if (const char *env = getenv("QMC_LEAF_CW")) {
-    const int v = atoi(env);
-    if (v >= 1 && v <= p.nw) p.cw = v;
-  }
-  p.cw = (int)std::min<int64_t>(p.cw, tct);
-  while (p.nw % p.cw) --p.cw;
-  p.sw = p.nw / p.cw;                         // and over subtree groups
-  p.gy = (int)ceil_div(tct, p.cw);
-  p.gx = (int)ceil_div(G.nsub, p.sw * spw);
+  p.nw = mode == kModeGrad ? 2 : 4;  // waves per workgroup, each on its own subtrees
+  p.gy = (int)tct;
+  p.gx = (int)ceil_div(G.nsub, (int64_t)p.nw * spw);
   return p;
 }
 
@@ -383,7 +509,9 @@ hipError_t launch_leaf(const Geometry &G, int mode, const qmc_integrand &f, cons
     a.up_row0[u] = (int)L.uoff;
     a.up_mask[u] = (1 << L.nb) - 1;
   }
+  a.taus = 0;
   for (int I = 0; I < G.split; ++I) {
+    a.taus |= (uint64_t)G.lev[I].tau << (8 * I);
     a.lv[I].tau = G.lev[I].tau;
     a.lv[I].off = (int)G.lev[I].off;
     a.lv[I].j0 = G.lev[I].j0;
@@ -396,15 +524,13 @@ hipError_t launch_leaf(const Geometry &G, int mode, const qmc_integrand &f, cons
   a.sigma = g_scale(f, mode);
   a.gc = (float)f.c;
   a.gscale = o.gscale;
-  a.cw = lp.cw;
-  a.sw = lp.sw;
   a.gy = lp.gy;
   a.nparts = lp.gx * lp.gy;
   // largest |x| of a point value after the map (bounds the cos argument)
   a.xmax = G.map == QMC_MAP_INVNORM ? 8.5f : 1.0f;
   dim3 grid(lp.gx, lp.gy, nr);
   const size_t lds =
-      sizeof(float) * (size_t)G.jlow * kTileT * (lp.cw + (mode == kModeGrad ? lp.nw : 0));
+      sizeof(float) * kTileT * ((size_t)G.jlow + kLdsPadRows + (mode == kModeGrad ? (size_t)lp.nw * G.jlow : 0));
   // the matvec mode does not evaluate g
   const int gf = mode == kModeStoreY ? QMC_G_ID : f.g;
   const bool fuse0 = G.split >= 1 && G.lev[0].tau == 1;

@@ -32,6 +32,8 @@ constexpr int kMaxLevels = kMaxM + 1;
 constexpr int kMaxSplit = 6;       // at most 64 leaves per subtree
 constexpr int kTileT = 64;         // columns per wave in the leaf kernels
 constexpr int kMaxLowRows = 64;    // rows of A kept in LDS by the leaf kernels
+constexpr int kLdsPadRows = 8;   // zero rows after the leaf kernel's rows of A in LDS
+constexpr int kTablePad = 64;    // floats after the point tables (the leaf's batched loads over-read)
 
 struct Level {
   int32_t tau;     // coordinates in the level
@@ -113,12 +115,17 @@ struct LeafLevel {
   int32_t tau, off, j0, pad;   // coordinates, record offset (floats), first coordinate
 };
 
+constexpr int kMaxUpPadded = (kMaxLevels + 7) / 8 * 8;
+
 struct LeafArgs {
-  int32_t t, tct, nsub, rec, spw, gx, gy, nw, cw, sw, jlow, r0, nup, nparts;
+  int32_t t, tct, nsub, rec, spw, gx, gy, nw, jlow, r0, nup, nparts;
   float xmax;                   // bound on |x| of every point value
-  int32_t up_row0[kMaxLevels];  // first U row of each upper level (per shift)
-  int32_t up_mask[kMaxLevels];  // n_I - 1
+  // first U row and n_I - 1 of each upper level (per shift); the entries past
+  // nup are zero, and the arrays are padded to whole batches of the root loads
+  int32_t up_row0[kMaxUpPadded];
+  int32_t up_mask[kMaxUpPadded];
   LeafLevel lv[kMaxSplit];
+  uint64_t taus;                // tau_I of the lower levels, one byte per level (level I at bit 8 I)
   int64_t tstride, ustride, lda, ldu, ldy;
   float sigma;                  // y' = sigma y: 1/(2 pi) for cos, c log2(e) for exp
   float gc;                     // parameter c of exp(c y)
@@ -141,10 +148,9 @@ struct LeafOut {
 
 struct LeafPlan {
   int gx;              // workgroups along the subtree axis
-  int gy;              // workgroups along the column-tile axis
+  int gy;              // workgroups along the column-tile axis (one tile each)
   int spw;             // subtrees per wave
-  int nw;              // waves per workgroup = cw x sw
-  int cw, sw;          // column tiles x subtree groups per workgroup
+  int nw;              // waves per workgroup
 };
 LeafPlan leaf_plan(const Geometry &G, int t, int nr, int mode);
 
