@@ -148,8 +148,8 @@ size_t carve(const qmc::Geometry &G, int op, int t, const qmc_integrand *f, int 
   Carve c{base};
   const int64_t ldu = round_up(t, kTileT);
   const int64_t tct = ceil_div(t, kTileT);
-  const LeafPlan lp = leaf_plan(G, t, nr, kModeSum);
-  const LeafPlan lg = leaf_plan(G, t, nr, kModeGrad);
+  const LeafPlan lp = leaf_plan(G, t, nr, kModeSum, f->g);
+  const LeafPlan lg = leaf_plan(G, t, nr, kModeGrad, f->g);
   wk = Work{};
   wk.tables = c.take<float>((size_t)nr * G.table_total + kTablePad);
   wk.U = c.take<float>((size_t)nr * G.urows * ldu);
@@ -453,6 +453,7 @@ qmc_status qmc_workspace_size(qmc_points p, int32_t op, int32_t t, const qmc_int
   } else {
     f = &dflt;
   }
+  DeviceGuard dg(p->device);  // the leaf plan queries the device's occupancy
   Work wk;
   *bytes = carve(p->G, op, t, f, op == kOpMatvec ? 1 : p->G.R, nullptr, wk);
   return QMC_OK;
@@ -483,7 +484,7 @@ qmc_status qmc_reduced_matvec(qmc_points p, int32_t r, const float *A, int32_t t
   LeafOut o{};
   o.Y = Y;
   o.ldy = ldy;
-  QMC_HIP(launch_leaf(G, kModeStoreY, fid, wk.tables, wk.U, 1, r, A, t, lda, ldu, leaf_plan(G, t, 1, kModeStoreY), o, st),
+  QMC_HIP(launch_leaf(G, kModeStoreY, fid, wk.tables, wk.U, 1, r, A, t, lda, ldu, leaf_plan(G, t, 1, kModeStoreY, QMC_G_ID), o, st),
           "leaf launch");
   return QMC_OK;
 }
@@ -510,8 +511,8 @@ static qmc_status estimate_impl(qmc_points p, const float *A, int32_t t, int64_t
   carve(G, op, t, f, nr, base, wk);
   const int64_t ldu = round_up(t, kTileT);
   const int tct = (int)ceil_div(t, kTileT);
-  const LeafPlan lp = leaf_plan(G, t, nr, kModeSum);
-  const LeafPlan lg = leaf_plan(G, t, nr, kModeGrad);
+  const LeafPlan lp = leaf_plan(G, t, nr, kModeSum, f->g);
+  const LeafPlan lg = leaf_plan(G, t, nr, kModeGrad, f->g);
   const bool sep = f->h == QMC_H_ID;
   const double inv_nt = 1.0 / ((double)G.N * (double)t);
 
@@ -530,7 +531,8 @@ static qmc_status estimate_impl(qmc_points p, const float *A, int32_t t, int64_t
   } else {
     // per-point sums over all columns, then h and the mean
     o.ppart = wk.ppart;
-    QMC_HIP(launch_leaf(G, kModePoint, *f, wk.tables, wk.U, nr, 0, A, t, lda, ldu, lp, o, st), "leaf launch");
+    const LeafPlan lpp = leaf_plan(G, t, nr, kModePoint, f->g);
+    QMC_HIP(launch_leaf(G, kModePoint, *f, wk.tables, wk.U, nr, 0, A, t, lda, ldu, lpp, o, st), "leaf launch");
     const int64_t blocks = point_h_blocks(G);
     QMC_HIP(launch_point_h(G, *f, wk.ppart, nr, tct, t, wk.ppartial, blocks, grad ? wk.hd : nullptr,
                            1.0, st),

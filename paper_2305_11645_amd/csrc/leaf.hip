@@ -28,12 +28,16 @@
 //          per wave in LDS, the subtree-root sums S_{L'} go to memory.
 #include <algorithm>
 #include <cstdlib>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 #include "qmc_internal.h"
 
 namespace qmc {
 
 constexpr int kRootBatch = 8;  // upper-level rows of a subtree root loaded together (summing mode)
+constexpr int kStagePerThread = 8;  // elements of A per thread and staging pass
 static_assert(kMaxUpPadded % kRootBatch == 0, "root batches must tile the padded level arrays");
 
 // cos and sin take the angle in revolutions on v_cos / v_sin; v_fract reduces
@@ -60,119 +64,161 @@ __device__ __forceinline__ float g_der(float ys, float c) {
   return 1.0f;
 }
 
-// Summing mode, lean form.  Only the per-level counts tau_I travel with the
-// kernel (one byte per level); the record offset and the first row of A of a
-// level follow from the counts while descending, so few scalar registers stay
-// live.  The point values of up to kBatchFloats nodes x coordinates and their
-// rows of A are requested together, then consumed: one memory round trip per
-// batch instead of one per coordinate.  The scalar loads may read up to 31
-// floats past a level's block (the point tables carry padding at their end);
-// the LDS reads of A up to 7 rows past a level's rows (kLdsPadRows zero rows
-// follow the staged rows).
+// Summing mode, lean form.  A lane carries CPL columns of A (the wave 64 CPL
+// columns), so every point value loaded into a scalar register feeds CPL
+// multiply-adds.  Only the per-level counts tau_I travel with the kernel (one
+// byte per level); the record offset and the first row of A of a level follow
+// from the counts while descending, so few scalar registers stay live.  The
+// point values of up to kBatchFloats nodes x coordinates and their rows of A
+// are requested together, then consumed: one memory round trip per batch
+// instead of one per coordinate.  The scalar loads may read up to 31 floats
+// past a level's block (the point tables carry padding at their end); the LDS
+// reads of A up to 7 rows past a level's rows (kLdsPadRows zero rows follow
+// the staged rows).
 constexpr int kBatchFloats = 32;
 
-template <int NC>
+template <int NC, int CPL>
 constexpr int batch_coords() {
-  return NC >= kBatchFloats ? 1 : (kBatchFloats / NC < 8 ? kBatchFloats / NC : 8);
+  constexpr int cap = 8 / CPL;  // rows of A per batch (B x CPL registers)
+  return NC >= kBatchFloats ? 1 : (kBatchFloats / NC < cap ? kBatchFloats / NC : cap);
 }
 
-// y[c] += x[c] a for c < NC, reading x in chunks of at most kBatchFloats.
-template <int NC>
-__device__ __forceinline__ void axpy_chunks(float *y, const float *__restrict__ x, float a) {
-  constexpr int CH = NC < kBatchFloats ? NC : kBatchFloats;
+template <int N>
+__device__ __forceinline__ void keep_scalar(const float (&v)[N]) {
 #pragma unroll
-  for (int h = 0; h < NC / CH; ++h) {
-    float xs[CH];
-#pragma unroll
-    for (int i = 0; i < CH; ++i) xs[i] = x[h * CH + i];
-#pragma unroll
-    for (int i = 0; i < CH; ++i) asm volatile("" ::"s"(xs[i]));
-#pragma unroll
-    for (int i = 0; i < CH; ++i) y[h * CH + i] = fmaf(xs[i], a, y[h * CH + i]);
-  }
+  for (int i = 0; i < N; ++i) asm volatile("" ::"s"(v[i]));
 }
 
-template <int LP, int L, int LAST>
-__device__ __forceinline__ void descend_lean(float (&y)[1 << LP], const float *__restrict__ rec,
+template <int LP, int L, int LAST, int CPL>
+__device__ __forceinline__ void descend_lean(float (&y)[CPL][1 << LP], const float *__restrict__ rec,
                                              int &xo, int &j0, uint64_t taus, const float *Al) {
   if constexpr (L >= LAST) {
     constexpr int NC = 1 << (LP - L);
     constexpr int H = NC / 2;
-    constexpr int B = batch_coords<NC>();
+    constexpr int B = batch_coords<NC, CPL>();
+    constexpr int RS = CPL * kTileT;  // LDS row stride; column q of the lane at q kTileT
     const int tau = (int)((taus >> (8 * L)) & 0xff);
     j0 -= tau;
     if (tau == 0) {
 #pragma unroll
-      for (int c = 0; c < H; ++c) y[c + H] = y[c];
+      for (int q = 0; q < CPL; ++q)
+#pragma unroll
+        for (int c = 0; c < H; ++c) y[q][c + H] = y[q][c];
     } else {
       const float *x = rec + xo;
-      const float *Aj = Al + j0 * kTileT;  // row stride kTileT; kLdsPadRows zero rows follow
+      const float *Aj = Al + j0 * RS;
       if constexpr (B * NC <= kBatchFloats) {
         // first batch: coordinate 0 forms the children (the tile step)
-        float xs[B * NC], av[B];
+        float xs[B * NC], av[B][CPL];
 #pragma unroll
         for (int i = 0; i < B * NC; ++i) xs[i] = x[i];
 #pragma unroll
-        for (int i = 0; i < B; ++i) av[i] = Aj[i * kTileT];
+        for (int i = 0; i < B; ++i)
+#pragma unroll
+          for (int q = 0; q < CPL; ++q) av[i][q] = Aj[i * RS + q * kTileT];
         // consume every value here, so no load sinks into the guarded uses
+        keep_scalar(xs);
 #pragma unroll
-        for (int i = 0; i < B * NC; ++i) asm volatile("" ::"s"(xs[i]));
+        for (int i = 0; i < B; ++i)
 #pragma unroll
-        for (int i = 0; i < B; ++i) asm volatile("" ::"v"(av[i]));
+          for (int q = 0; q < CPL; ++q) asm volatile("" ::"v"(av[i][q]));
 #pragma unroll
-        for (int c = 0; c < H; ++c) y[c + H] = fmaf(xs[c + H], av[0], y[c]);
+        for (int q = 0; q < CPL; ++q) {
 #pragma unroll
-        for (int c = 0; c < H; ++c) y[c] = fmaf(xs[c], av[0], y[c]);
+          for (int c = 0; c < H; ++c) y[q][c + H] = fmaf(xs[c + H], av[0][q], y[q][c]);
+#pragma unroll
+          for (int c = 0; c < H; ++c) y[q][c] = fmaf(xs[c], av[0][q], y[q][c]);
+        }
 #pragma unroll
         for (int i = 1; i < B; ++i) {
           if (i >= tau) break;
 #pragma unroll
-          for (int c = 0; c < NC; ++c) y[c] = fmaf(xs[i * NC + c], av[i], y[c]);
+          for (int q = 0; q < CPL; ++q)
+#pragma unroll
+            for (int c = 0; c < NC; ++c) y[q][c] = fmaf(xs[i * NC + c], av[i][q], y[q][c]);
         }
 #pragma unroll 1
         for (int jb = B; jb < tau; jb += B) {
 #pragma unroll
           for (int i = 0; i < B * NC; ++i) xs[i] = x[jb * NC + i];
 #pragma unroll
-          for (int i = 0; i < B; ++i) av[i] = Aj[(jb + i) * kTileT];
+          for (int i = 0; i < B; ++i)
 #pragma unroll
-          for (int i = 0; i < B * NC; ++i) asm volatile("" ::"s"(xs[i]));
+            for (int q = 0; q < CPL; ++q) av[i][q] = Aj[(jb + i) * RS + q * kTileT];
+          keep_scalar(xs);
 #pragma unroll
-          for (int i = 0; i < B; ++i) asm volatile("" ::"v"(av[i]));
+          for (int i = 0; i < B; ++i)
+#pragma unroll
+            for (int q = 0; q < CPL; ++q) asm volatile("" ::"v"(av[i][q]));
 #pragma unroll
           for (int i = 0; i < B; ++i) {
             if (jb + i >= tau) break;
 #pragma unroll
-            for (int c = 0; c < NC; ++c) y[c] = fmaf(xs[i * NC + c], av[i], y[c]);
+            for (int q = 0; q < CPL; ++q)
+#pragma unroll
+              for (int c = 0; c < NC; ++c) y[q][c] = fmaf(xs[i * NC + c], av[i][q], y[q][c]);
           }
         }
-      } else {  // NC = 64 (level 0 with more than one coordinate): one at a time, in chunks
-        const float a0 = Aj[0];
-        float z[H];
+      } else {
+        // NC = 64 (level 0 with more than one coordinate): one coordinate at a
+        // time, its 64 point values in two chunks of 32.  The tile step forms
+        // the upper half first, while the lower half still holds the parents.
+        static_assert(NC == 2 * kBatchFloats, "chunking assumes 64 nodes");
+        float a[CPL], xs[kBatchFloats];
 #pragma unroll
-        for (int c = 0; c < H; ++c) z[c] = y[c];
-        axpy_chunks<H>(y, x, a0);
-        axpy_chunks<H>(z, x + H, a0);
+        for (int q = 0; q < CPL; ++q) a[q] = Aj[q * kTileT];
 #pragma unroll
-        for (int c = 0; c < H; ++c) y[c + H] = z[c];
+        for (int i = 0; i < H; ++i) xs[i] = x[H + i];
+        keep_scalar(xs);
+#pragma unroll
+        for (int q = 0; q < CPL; ++q)
+#pragma unroll
+          for (int c = 0; c < H; ++c) y[q][c + H] = fmaf(xs[c], a[q], y[q][c]);
+#pragma unroll
+        for (int i = 0; i < H; ++i) xs[i] = x[i];
+        keep_scalar(xs);
+#pragma unroll
+        for (int q = 0; q < CPL; ++q)
+#pragma unroll
+          for (int c = 0; c < H; ++c) y[q][c] = fmaf(xs[c], a[q], y[q][c]);
 #pragma unroll 1
-        for (int jj = 1; jj < tau; ++jj) axpy_chunks<NC>(y, x + jj * NC, Aj[jj * kTileT]);
+        for (int jj = 1; jj < tau; ++jj) {
+#pragma unroll
+          for (int q = 0; q < CPL; ++q) a[q] = Aj[jj * RS + q * kTileT];
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+#pragma unroll
+            for (int i = 0; i < H; ++i) xs[i] = x[jj * NC + h * H + i];
+            keep_scalar(xs);
+#pragma unroll
+            for (int q = 0; q < CPL; ++q)
+#pragma unroll
+              for (int c = 0; c < H; ++c) y[q][h * H + c] = fmaf(xs[c], a[q], y[q][h * H + c]);
+          }
+        }
       }
       xo += tau * NC;
     }
-    descend_lean<LP, L - 1, LAST>(y, rec, xo, j0, taus, Al);
+    descend_lean<LP, L - 1, LAST, CPL>(y, rec, xo, j0, taus, Al);
   }
 }
 
 // Level 0 with a single coordinate, fused with g: leaf c and c + H0 come from
 // the level-1 node c.  The 2 H0 point values are read in halves of at most
-// kBatchFloats.  Returns the FP32 sum of g over the subtree's leaves.
-template <int LP, int GF, bool NEAR>
-__device__ __forceinline__ float leaf_block(const float (&y)[1 << LP], const float *__restrict__ x0,
-                                            float a0) {
+// kBatchFloats.  s[q] receives the FP32 sum of g over the subtree's leaves in
+// column q of the lane.
+template <int LP, int GF, bool NEAR, int CPL>
+__device__ __forceinline__ void leaf_block(const float (&y)[CPL][1 << LP],
+                                           const float *__restrict__ x0, const float (&a0)[CPL],
+                                           float (&s)[CPL]) {
   constexpr int H0 = (1 << LP) / 2;
   constexpr int HB = H0 < kBatchFloats / 2 ? H0 : kBatchFloats / 2;
-  float s = 0.f;
+  constexpr int NA = 4;  // independent partial sums per column (breaks the add chain)
+  float sp[CPL][NA];
+#pragma unroll
+  for (int q = 0; q < CPL; ++q)
+#pragma unroll
+    for (int k = 0; k < NA; ++k) sp[q][k] = 0.f;
 #pragma unroll
   for (int h = 0; h < H0 / HB; ++h) {
     float xa[HB], xb[HB];
@@ -181,21 +227,28 @@ __device__ __forceinline__ float leaf_block(const float (&y)[1 << LP], const flo
       xa[i] = x0[h * HB + i];
       xb[i] = x0[H0 + h * HB + i];
     }
-#pragma unroll
-    for (int i = 0; i < HB; ++i) asm volatile("" ::"s"(xa[i]), "s"(xb[i]));
+    keep_scalar(xa);
+    keep_scalar(xb);
 #pragma unroll
     for (int i = 0; i < HB; ++i) {
       const int c = h * HB + i;
-      if (NEAR) {
-        s += g_val_near<GF>(fmaf(xa[i], a0, y[c]));
-        s += g_val_near<GF>(fmaf(xb[i], a0, y[c]));
-      } else {
-        s += g_val<GF>(fmaf(xa[i], a0, y[c]));
-        s += g_val<GF>(fmaf(xb[i], a0, y[c]));
+#pragma unroll
+      for (int q = 0; q < CPL; ++q) {
+        float ga, gb;
+        if (NEAR) {
+          ga = g_val_near<GF>(fmaf(xa[i], a0[q], y[q][c]));
+          gb = g_val_near<GF>(fmaf(xb[i], a0[q], y[q][c]));
+        } else {
+          ga = g_val<GF>(fmaf(xa[i], a0[q], y[q][c]));
+          gb = g_val<GF>(fmaf(xb[i], a0[q], y[q][c]));
+        }
+        sp[q][(2 * c) % NA] += ga;
+        sp[q][(2 * c + 1) % NA] += gb;
       }
     }
   }
-  return s;
+#pragma unroll
+  for (int q = 0; q < CPL; ++q) s[q] = (sp[q][0] + sp[q][1]) + (sp[q][2] + sp[q][3]);
 }
 
 // One level of the descent, one coordinate at a time (the modes that keep
@@ -289,7 +342,7 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-template <int LP, int MODE, int GF, bool FUSE0>
+template <int LP, int MODE, int GF, bool FUSE0, int CPL>
 __global__ __launch_bounds__(256) void leaf_kernel(LeafArgs a, const float *__restrict__ tables,
                                                    const float *__restrict__ U,
                                                    const float *__restrict__ A,
@@ -299,35 +352,65 @@ __global__ __launch_bounds__(256) void leaf_kernel(LeafArgs a, const float *__re
                                                    float *__restrict__ Sroot,
                                                    const float *__restrict__ hd) {
   constexpr int NL = 1 << LP;
+  constexpr int CW = CPL * kTileT;  // columns of A per workgroup (CPL per lane)
+  static_assert(CPL == 1 || MODE == kModeSum, "several columns per lane: summing mode only");
   extern __shared__ float smem[];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-  // every wave of the workgroup works on column tile by, on its own subtrees
+  // every wave of the workgroup works on column tile ct (CW columns), on its
+  // own subtrees; lane column q is ct CW + q 64 + lane
   const int bx = blockIdx.x, ct = blockIdx.y, rl = blockIdx.z;
-  const int col = ct * kTileT + lane;
-  const bool live = col < a.t;
+  const int col = ct * CW + lane;
+  bool live[CPL];
+#pragma unroll
+  for (int q = 0; q < CPL; ++q) live[q] = col + q * kTileT < a.t;
   const int jlow = a.jlow;
 
   // rows 0 .. jlow-1 of sigma A for the tile, then kLdsPadRows zero rows
+  // Every load of a pass is issued before the first is used (addresses are
+  // clamped into A, out-of-range elements are then replaced by 0), so a pass
+  // costs one memory round trip.
+  __shared__ double red[4];  // per-wave sums
+  __shared__ int arrived;     // waves done (counted in LDS)
+  if (tid == 0) arrived = 0;  // visible to all after the barrier below
   float *Alds = smem;
-  for (int e = tid; e < (jlow + kLdsPadRows) * kTileT; e += blockDim.x) {
-    const int jr = e / kTileT, cl = ct * kTileT + (e % kTileT);
-    Alds[e] = jr < jlow && cl < a.t ? a.sigma * A[(int64_t)jr * a.lda + cl] : 0.f;
+  const int stage_total = (jlow + kLdsPadRows) * CW;
+  for (int e0 = 0; e0 < stage_total; e0 += kStagePerThread * (int)blockDim.x) {
+    float v[kStagePerThread];
+#pragma unroll
+    for (int k = 0; k < kStagePerThread; ++k) {
+      const int e = e0 + k * (int)blockDim.x + tid;
+      const int jr = e / CW, cl = ct * CW + (e % CW);
+      const int jrc = min(jr, max(jlow - 1, 0)), clc = min(cl, a.t - 1);
+      const float x = A[(int64_t)jrc * a.lda + clc];
+      v[k] = e < stage_total && jr < jlow && cl < a.t ? a.sigma * x : 0.f;
+    }
+#pragma unroll
+    for (int k = 0; k < kStagePerThread; ++k) {
+      const int e = e0 + k * (int)blockDim.x + tid;
+      if (e < stage_total) Alds[e] = v[k];
+    }
   }
-  float *dAl = smem + (jlow + kLdsPadRows) * kTileT + w * jlow * kTileT;
+  float *dAl = smem + (jlow + kLdsPadRows) * CW + w * jlow * kTileT;
   if (MODE == kModeGrad)
     for (int e = lane; e < jlow * kTileT; e += 64) dAl[e] = 0.f;
   __syncthreads();
-  const float *Al = Alds + lane;  // this lane's column; row stride kTileT
+  const float *Al = Alds + lane;  // this lane's first column; row stride CW
 
   // For cos: the subtree root is reduced to [0, 1) revolutions once; if the
   // lower levels add at most 250 revolutions in magnitude on every lane, the
   // leaves stay inside v_cos's domain and need no further reduction.
   bool near = false;
   if (GF == QMC_G_COS) {
-    float bound = 0.f;
-    for (int j = 0; j < jlow; ++j) bound += fabsf(Al[j * kTileT]);
+    float bound = 0.f, bq[CPL];
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) bq[q] = 0.f;
+    for (int j = 0; j < jlow; ++j)
+#pragma unroll
+      for (int q = 0; q < CPL; ++q) bq[q] += fabsf(Al[j * CW + q * kTileT]);
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) bound = fmaxf(bound, bq[q]);
     near = __all(bound * a.xmax < 250.0f);
   }
 
@@ -335,58 +418,84 @@ __global__ __launch_bounds__(256) void leaf_kernel(LeafArgs a, const float *__re
   const float *Ub = U + (int64_t)rl * a.ustride;
   double acc = 0.0;
 
-  const int first = (bx * a.nw + w) * a.spw;
-  const int last = min(first + a.spw, a.nsub);
-  for (int rho = first; rho < last; ++rho) {
+  // the workgroup's share of the subtrees, dealt to its waves in turn
+  // (balanced: the first sub_rem workgroups take sub_per + 1 subtrees)
+  const int first = bx * a.sub_per + min(bx, a.sub_rem);
+  const int last = first + a.sub_per + (bx < a.sub_rem ? 1 : 0);
+  for (int rho = first + w; rho < last; rho += a.nw) {
     const float *rec = tab + (int64_t)rho * a.rec;
 
     // subtree root: the upper levels' rows, requested RB at a time
     constexpr int RB = MODE == kModeSum ? kRootBatch : 1;
-    float root = 0.f;
+    float root[CPL];
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) root[q] = 0.f;
 #pragma unroll 1
     for (int u0 = 0; u0 < a.nup; u0 += RB) {
-      float rv[RB];
+      float rv[RB][CPL];
 #pragma unroll
-      for (int i = 0; i < RB; ++i)  // entries past nup are zero: they read row 0
-        rv[i] = Ub[(int64_t)(a.up_row0[u0 + i] + (rho & a.up_mask[u0 + i])) * a.ldu + col];
+      for (int i = 0; i < RB; ++i) {  // entries past nup are zero: they read row 0
+        // uniform row address (scalar unit), then this lane's column
+        const float *row = Ub + a.up_off[u0 + i] + (uint64_t)(uint32_t)(rho & a.up_mask[u0 + i]) * a.ldu32;
 #pragma unroll
-      for (int i = 0; i < RB; ++i) asm volatile("" ::"v"(rv[i]));
+        for (int q = 0; q < CPL; ++q) rv[i][q] = row[col + q * kTileT];
+      }
 #pragma unroll
       for (int i = 0; i < RB; ++i)
-        if (u0 + i < a.nup) root += rv[i];
+#pragma unroll
+        for (int q = 0; q < CPL; ++q) asm volatile("" ::"v"(rv[i][q]));
+#pragma unroll
+      for (int i = 0; i < RB; ++i)
+        if (u0 + i < a.nup)
+#pragma unroll
+          for (int q = 0; q < CPL; ++q) root[q] += rv[i][q];
     }
-    if (GF == QMC_G_COS) root = __builtin_amdgcn_fractf(root);
+    if (GF == QMC_G_COS)
+#pragma unroll
+      for (int q = 0; q < CPL; ++q) root[q] = __builtin_amdgcn_fractf(root[q]);
 
-    float y[NL];
-    y[0] = root;
-    if (MODE == kModeSum) {
+    if constexpr (MODE == kModeSum) {
       // the level counts are re-read per subtree (opaque to the compiler), so
       // the per-level offsets are not hoisted into registers held for the
       // whole loop
       uint64_t taus = a.taus;
       asm volatile("" : "+s"(taus));
       int xo = 0, j0 = jlow;
-      float s = 0.f;
-      if constexpr (FUSE0) {
-        descend_lean<LP, LP - 1, 1>(y, rec, xo, j0, taus, Al);
-        const float a0 = Al[0];  // level 0 is row 0
-        s = near ? leaf_block<LP, GF, true>(y, rec + xo, a0) : leaf_block<LP, GF, false>(y, rec + xo, a0);
-      } else {
-        descend_lean<LP, LP - 1, 0>(y, rec, xo, j0, taus, Al);
+      float y[CPL][NL], s[CPL];
 #pragma unroll
-        for (int c = 0; c < NL; ++c) s += g_val<GF>(y[c]);
+      for (int q = 0; q < CPL; ++q) y[q][0] = root[q];
+      if constexpr (FUSE0) {
+        descend_lean<LP, LP - 1, 1, CPL>(y, rec, xo, j0, taus, Al);
+        float a0[CPL];  // level 0 is row 0
+#pragma unroll
+        for (int q = 0; q < CPL; ++q) a0[q] = Al[q * kTileT];
+        if (near) leaf_block<LP, GF, true, CPL>(y, rec + xo, a0, s);
+        else leaf_block<LP, GF, false, CPL>(y, rec + xo, a0, s);
+      } else {
+        descend_lean<LP, LP - 1, 0, CPL>(y, rec, xo, j0, taus, Al);
+#pragma unroll
+        for (int q = 0; q < CPL; ++q) {
+          s[q] = 0.f;
+#pragma unroll
+          for (int c = 0; c < NL; ++c) s[q] += g_val<GF>(y[q][c]);
+        }
       }
-      if (live) acc += (double)s;
+#pragma unroll
+      for (int q = 0; q < CPL; ++q)
+        if (live[q]) acc += (double)s[q];
     } else {
+      float y[NL];
+      y[0] = root[0];
+      const bool live0 = live[0];
       descend_to<LP, LP - 1, 0>(y, rec, a.lv, Alds, kTileT, lane);
       if (MODE == kModePoint) {
         float v[64];
 #pragma unroll
-        for (int c = 0; c < 64; ++c) v[c] = (c < NL && live) ? g_val<GF>(y[c < NL ? c : 0]) : 0.f;
+        for (int c = 0; c < 64; ++c) v[c] = (c < NL && live0) ? g_val<GF>(y[c < NL ? c : 0]) : 0.f;
         transpose_step<32>(v, lane);
         if (lane < NL) ppart[(((int64_t)rl * a.tct + ct) * a.nsub + rho) * NL + lane] = v[0];
       } else if (MODE == kModeStoreY) {
-        if (live) {
+        if (live0) {
 #pragma unroll
           for (int c = 0; c < NL; ++c) Y[((int64_t)rho + (int64_t)c * a.nsub) * a.ldy + col] = y[c];
         }
@@ -398,30 +507,35 @@ __global__ __launch_bounds__(256) void leaf_kernel(LeafArgs a, const float *__re
         for (int c = 0; c < NL; ++c) {
           if (hd == nullptr) s += g_val<GF>(y[c]);
           const float fac = hk ? hk[c] : 1.0f;
-          S[c] = live ? (float)(a.gscale * (double)(fac * g_der<GF>(y[c], a.gc))) : 0.f;
+          S[c] = live0 ? (float)(a.gscale * (double)(fac * g_der<GF>(y[c], a.gc))) : 0.f;
         }
-        if (live && hd == nullptr) acc += (double)s;
+        if (live0 && hd == nullptr) acc += (double)s;
         ascend_all<LP, 0>(S, rec, a.lv, dAl, lane);
-        if (live) Sroot[((int64_t)rl * 2 * a.nsub + rho) * a.ldu + col] = S[0];
+        if (live0) Sroot[((int64_t)rl * 2 * a.nsub + rho) * a.ldu + col] = S[0];
       }
     }
   }
 
   if (MODE == kModeSum || MODE == kModeGrad) {
-    __shared__ double red[4];
+    // One FP64 partial per workgroup without a barrier: each wave leaves its
+    // sum in LDS and counts itself in; the last to arrive adds the sums in
+    // wave order (deterministic) and writes the partial.
     const double wsum = wave_sum(acc);
-    if (lane == 0) red[w] = wsum;
-    __syncthreads();
-    if (tid == 0) {
-      double tot = red[0];
-      for (int q = 1; q < a.nw; ++q) tot += red[q];
-      partial[(int64_t)rl * a.nparts + bx * a.gy + ct] = tot;
+    if (lane == 0) {
+      red[w] = wsum;
+      __threadfence_block();
+      if (atomicAdd(&arrived, 1) == a.nw - 1) {
+        __threadfence_block();
+        double tot = red[0];
+        for (int q = 1; q < a.nw; ++q) tot += red[q];
+        partial[(int64_t)rl * a.nparts + bx * a.gy + ct] = tot;
+      }
     }
   }
   if (MODE == kModeGrad) {
     __syncthreads();
     // sum the per-wave dA accumulators of the workgroup
-    const float *base = smem + (jlow + kLdsPadRows) * kTileT;
+    const float *base = smem + (jlow + kLdsPadRows) * CW;
     const int64_t st = (int64_t)jlow * kTileT;
     for (int e = tid; e < st; e += blockDim.x) {
       float v = 0.f;
@@ -431,55 +545,130 @@ __global__ __launch_bounds__(256) void leaf_kernel(LeafArgs a, const float *__re
   }
 }
 
-LeafPlan leaf_plan(const Geometry &G, int t, int nr, int mode) {
+static size_t leaf_lds_bytes(const Geometry &G, int mode, int cpl, int nw);
+static const void *leaf_fn(const Geometry &G, int mode, int gf, int cpl);
+static int64_t resident_workgroups(const void *fn, int threads, size_t lds);
+
+LeafPlan leaf_plan(const Geometry &G, int t, int nr, int mode, int gf) {
   const int64_t tct = ceil_div(t, kTileT);
-  const int64_t units = G.nsub * tct * nr;  // subtree x column-tile pieces
+  LeafPlan p;
+  // the summing mode can give each lane two columns (QMC_LEAF_CPL=2), unless
+  // the lane would then hold two full 64-leaf arrays (level 0 not fused)
+  const bool fuse0 = G.split >= 1 && G.lev[0].tau == 1;
+  const bool two_ok = mode == kModeSum && (fuse0 || G.split < kMaxSplit);
+  p.cpl = 1;  // two columns per lane measured slower (lower occupancy); kept selectable
+  if (const char *env = getenv("QMC_LEAF_CPL")) {
+    const int v = atoi(env);
+    if (two_ok && (v == 1 || v == 2)) p.cpl = v;
+  }
+  if (p.cpl == 2 && tct < 2) p.cpl = 1;
+  p.gy = (int)ceil_div(tct, p.cpl);
+  p.nw = mode == kModeGrad ? 2 : 4;  // waves per workgroup, each on its own subtrees
+  const int64_t pairs = (int64_t)p.gy * nr;  // (shift, column tile) pairs
+  const int64_t units = G.nsub * pairs;      // subtree x column-tile pieces
+  // more subtrees per wave amortise the staging of A and the final reduction,
+  // as long as more than 8192 waves (eight per SIMD) remain to hide latency
   int spw = 1;
-  while (spw < 32 && units / (spw * 2) >= 16384) spw *= 2;
+  while (spw < 32 && units / (spw * 2) > 8192) spw *= 2;
   if (const char *env = getenv("QMC_LEAF_SPW")) {
     const int v = atoi(env);
     if (v >= 1 && v <= 1024) spw = v;
   }
-  LeafPlan p;
   p.spw = spw;
-  p.nw = mode == kModeGrad ? 2 : 4;  // waves per workgroup, each on its own subtrees
-  p.gy = (int)tct;
   p.gx = (int)ceil_div(G.nsub, (int64_t)p.nw * spw);
+  // A grid that needs only a few rounds of resident workgroups loses much of
+  // its time to the staging at the start of each round and to the last,
+  // partly filled round.  Then launch exactly one round instead: every
+  // resident workgroup takes an equal share of its pair's subtrees.
+  // (measured: a gain for the per-point mode, a loss for the summing mode,
+  // whose short waves overlap their start-up latency better)
+  bool one_round = mode == kModePoint;
+  if (const char *env = getenv("QMC_LEAF_ONE_ROUND")) one_round = atoi(env) != 0;
+  if (one_round) {
+    const void *fn = leaf_fn(G, mode, gf, p.cpl);
+    const int64_t cap = resident_workgroups(fn, 64 * p.nw, leaf_lds_bytes(G, mode, p.cpl, p.nw));
+    const int64_t wgs = pairs * p.gx;
+    if (cap > 0 && wgs > cap && wgs <= 4 * cap && pairs <= cap) {
+      const int64_t gx = std::min<int64_t>(cap / pairs, ceil_div(G.nsub, (int64_t)p.nw));
+      p.gx = (int)std::max<int64_t>(gx, 1);
+    }
+  }
   return p;
 }
 
+// The kernel instance for a geometry, mode, g and columns per lane.
 template <int LP, int MODE, bool F0>
-static void leaf_launch_g(int gf, dim3 grid, size_t lds, hipStream_t st, const LeafArgs &a,
-                          const float *tables, const float *U, const float *A, const LeafOut &o) {
-#define QMC_LEAF_LAUNCH(GF)                                                                       \
-  hipLaunchKernelGGL((leaf_kernel<LP, MODE, GF, F0>), grid, dim3(64 * a.nw), lds, st, a, tables, \
-                     U, A, o.partial, o.ppart, o.Y, o.dApart, o.Sroot, o.hd)
-  if (gf == QMC_G_COS) QMC_LEAF_LAUNCH(QMC_G_COS);
-  else if (gf == QMC_G_EXP) QMC_LEAF_LAUNCH(QMC_G_EXP);
-  else QMC_LEAF_LAUNCH(QMC_G_ID);
-#undef QMC_LEAF_LAUNCH
+static const void *leaf_fn_g(int gf, int cpl) {
+#define QMC_LEAF_FN(GF, CPL) reinterpret_cast<const void *>(&leaf_kernel<LP, MODE, GF, F0, CPL>)
+  if constexpr (MODE == kModeSum && (F0 || LP < kMaxSplit)) {
+    if (cpl == 2) {
+      if (gf == QMC_G_COS) return QMC_LEAF_FN(QMC_G_COS, 2);
+      if (gf == QMC_G_EXP) return QMC_LEAF_FN(QMC_G_EXP, 2);
+      return QMC_LEAF_FN(QMC_G_ID, 2);
+    }
+  }
+  if (gf == QMC_G_COS) return QMC_LEAF_FN(QMC_G_COS, 1);
+  if (gf == QMC_G_EXP) return QMC_LEAF_FN(QMC_G_EXP, 1);
+  return QMC_LEAF_FN(QMC_G_ID, 1);
+#undef QMC_LEAF_FN
 }
 
 template <int LP, int MODE>
-static void leaf_launch_f(bool fuse0, int gf, dim3 grid, size_t lds, hipStream_t st,
-                          const LeafArgs &a, const float *tables, const float *U, const float *A,
-                          const LeafOut &o) {
-  if constexpr (LP >= 1) {
-    if (fuse0) return leaf_launch_g<LP, MODE, true>(gf, grid, lds, st, a, tables, U, A, o);
+static const void *leaf_fn_f(bool fuse0, int gf, int cpl) {
+  if constexpr (LP >= 1 && MODE != kModeGrad) {
+    if (fuse0) return leaf_fn_g<LP, MODE, true>(gf, cpl);
   }
-  leaf_launch_g<LP, MODE, false>(gf, grid, lds, st, a, tables, U, A, o);
+  return leaf_fn_g<LP, MODE, false>(gf, cpl);
 }
 
 template <int LP>
-static void leaf_launch_m(int mode, bool fuse0, int gf, dim3 grid, size_t lds, hipStream_t st,
-                          const LeafArgs &a, const float *tables, const float *U, const float *A,
-                          const LeafOut &o) {
+static const void *leaf_fn_m(int mode, bool fuse0, int gf, int cpl) {
   switch (mode) {
-    case kModeSum: return leaf_launch_f<LP, kModeSum>(fuse0, gf, grid, lds, st, a, tables, U, A, o);
-    case kModePoint: return leaf_launch_f<LP, kModePoint>(fuse0, gf, grid, lds, st, a, tables, U, A, o);
-    case kModeStoreY: return leaf_launch_f<LP, kModeStoreY>(fuse0, gf, grid, lds, st, a, tables, U, A, o);
-    default: return leaf_launch_f<LP, kModeGrad>(false, gf, grid, lds, st, a, tables, U, A, o);
+    case kModeSum: return leaf_fn_f<LP, kModeSum>(fuse0, gf, cpl);
+    case kModePoint: return leaf_fn_f<LP, kModePoint>(fuse0, gf, cpl);
+    case kModeStoreY: return leaf_fn_f<LP, kModeStoreY>(fuse0, gf, cpl);
+    default: return leaf_fn_f<LP, kModeGrad>(fuse0, gf, cpl);
   }
+}
+
+static const void *leaf_fn(const Geometry &G, int mode, int gf, int cpl) {
+  if (mode == kModeStoreY) gf = QMC_G_ID;  // the matvec mode does not evaluate g
+  if (mode != kModeSum) cpl = 1;
+  const bool fuse0 = G.split >= 1 && G.lev[0].tau == 1;
+  switch (G.split) {
+    case 0: return leaf_fn_m<0>(mode, false, gf, cpl);
+    case 1: return leaf_fn_m<1>(mode, fuse0, gf, cpl);
+    case 2: return leaf_fn_m<2>(mode, fuse0, gf, cpl);
+    case 3: return leaf_fn_m<3>(mode, fuse0, gf, cpl);
+    case 4: return leaf_fn_m<4>(mode, fuse0, gf, cpl);
+    case 5: return leaf_fn_m<5>(mode, fuse0, gf, cpl);
+    default: return leaf_fn_m<6>(mode, fuse0, gf, cpl);
+  }
+}
+
+static size_t leaf_lds_bytes(const Geometry &G, int mode, int cpl, int nw) {
+  return sizeof(float) * kTileT *
+         ((size_t)cpl * (G.jlow + kLdsPadRows) + (mode == kModeGrad ? (size_t)nw * G.jlow : 0));
+}
+
+// Workgroups of a kernel instance that fit on the current device at once.
+static int64_t resident_workgroups(const void *fn, int threads, size_t lds) {
+  static std::mutex mu;
+  static std::map<std::tuple<int, const void *, int, size_t>, int64_t> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  const auto key = std::make_tuple(dev, fn, threads, lds);
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  int per_cu = 0, cus = 0;
+  int64_t cap = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds) == hipSuccess &&
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
+    cap = (int64_t)per_cu * cus;
+  (void)hipGetLastError();  // a failed query only disables the resident-grid choice
+  cache[key] = cap;
+  return cap;
 }
 
 float g_scale(const qmc_integrand &f, int mode) {
@@ -493,20 +682,24 @@ hipError_t launch_leaf(const Geometry &G, int mode, const qmc_integrand &f, cons
                        const float *U, int nr, int r0, const float *A, int t, int64_t lda,
                        int64_t ldu, const LeafPlan &lp, const LeafOut &o, hipStream_t st) {
   LaunchTimer tm("leaf", st);
+  // several columns per lane exist in the summing mode only; a plan made for
+  // another mode would leave column tiles out
+  if (lp.cpl != 1 && mode != kModeSum) return hipErrorInvalidValue;
   LeafArgs a{};
   a.t = t;
   a.tct = (int)ceil_div(t, kTileT);
   a.nsub = (int)G.nsub;
   a.rec = (int)G.rec;
-  a.spw = lp.spw;
   a.gx = lp.gx;
+  a.sub_per = (int)(G.nsub / lp.gx);
+  a.sub_rem = (int)(G.nsub % lp.gx);
   a.nw = lp.nw;
   a.jlow = G.jlow;
   a.r0 = r0;
   a.nup = G.nup;
   for (int u = 0; u < G.nup; ++u) {
     const Level &L = G.lev[G.up[u]];
-    a.up_row0[u] = (int)L.uoff;
+    a.up_off[u] = L.uoff * ldu;
     a.up_mask[u] = (1 << L.nb) - 1;
   }
   a.taus = 0;
@@ -520,6 +713,7 @@ hipError_t launch_leaf(const Geometry &G, int mode, const qmc_integrand &f, cons
   a.ustride = G.urows * ldu;
   a.lda = lda;
   a.ldu = ldu;
+  a.ldu32 = (uint32_t)ldu;
   a.ldy = o.ldy;
   a.sigma = g_scale(f, mode);
   a.gc = (float)f.c;
@@ -528,21 +722,13 @@ hipError_t launch_leaf(const Geometry &G, int mode, const qmc_integrand &f, cons
   a.nparts = lp.gx * lp.gy;
   // largest |x| of a point value after the map (bounds the cos argument)
   a.xmax = G.map == QMC_MAP_INVNORM ? 8.5f : 1.0f;
-  dim3 grid(lp.gx, lp.gy, nr);
-  const size_t lds =
-      sizeof(float) * kTileT * ((size_t)G.jlow + kLdsPadRows + (mode == kModeGrad ? (size_t)lp.nw * G.jlow : 0));
-  // the matvec mode does not evaluate g
-  const int gf = mode == kModeStoreY ? QMC_G_ID : f.g;
-  const bool fuse0 = G.split >= 1 && G.lev[0].tau == 1;
-  switch (G.split) {
-    case 0: leaf_launch_m<0>(mode, false, gf, grid, lds, st, a, tables, U, A, o); break;
-    case 1: leaf_launch_m<1>(mode, fuse0, gf, grid, lds, st, a, tables, U, A, o); break;
-    case 2: leaf_launch_m<2>(mode, fuse0, gf, grid, lds, st, a, tables, U, A, o); break;
-    case 3: leaf_launch_m<3>(mode, fuse0, gf, grid, lds, st, a, tables, U, A, o); break;
-    case 4: leaf_launch_m<4>(mode, fuse0, gf, grid, lds, st, a, tables, U, A, o); break;
-    case 5: leaf_launch_m<5>(mode, fuse0, gf, grid, lds, st, a, tables, U, A, o); break;
-    default: leaf_launch_m<6>(mode, fuse0, gf, grid, lds, st, a, tables, U, A, o); break;
-  }
+  const dim3 grid(lp.gx, lp.gy, nr), block(64 * lp.nw);
+  const size_t lds = leaf_lds_bytes(G, mode, lp.cpl, lp.nw);
+  const void *fn = leaf_fn(G, mode, f.g, lp.cpl);
+  void *args[] = {&a, (void *)&tables, (void *)&U, (void *)&A, (void *)&o.partial, (void *)&o.ppart,
+                  (void *)&o.Y, (void *)&o.dApart, (void *)&o.Sroot, (void *)&o.hd};
+  const hipError_t e = hipLaunchKernel(fn, grid, block, args, lds, st);
+  if (e != hipSuccess) return e;
   return hipGetLastError();
 }
 

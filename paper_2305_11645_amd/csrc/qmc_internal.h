@@ -118,15 +118,18 @@ struct LeafLevel {
 constexpr int kMaxUpPadded = (kMaxLevels + 7) / 8 * 8;
 
 struct LeafArgs {
-  int32_t t, tct, nsub, rec, spw, gx, gy, nw, jlow, r0, nup, nparts;
+  int32_t t, tct, nsub, rec, gx, gy, nw, jlow, r0, nup, nparts;
+  int32_t sub_per, sub_rem;     // subtrees per workgroup: nsub = sub_per gx + sub_rem
   float xmax;                   // bound on |x| of every point value
-  // first U row and n_I - 1 of each upper level (per shift); the entries past
-  // nup are zero, and the arrays are padded to whole batches of the root loads
-  int32_t up_row0[kMaxUpPadded];
+  // offset (floats) of the first U row and n_I - 1 of each upper level (per
+  // shift); the entries past nup are zero, and the arrays are padded to whole
+  // batches of the root loads
+  int64_t up_off[kMaxUpPadded];
   int32_t up_mask[kMaxUpPadded];
   LeafLevel lv[kMaxSplit];
   uint64_t taus;                // tau_I of the lower levels, one byte per level (level I at bit 8 I)
   int64_t tstride, ustride, lda, ldu, ldy;
+  uint32_t ldu32;               // ldu (< 2^32)
   float sigma;                  // y' = sigma y: 1/(2 pi) for cos, c log2(e) for exp
   float gc;                     // parameter c of exp(c y)
   double gscale;                // adjoint factor
@@ -136,7 +139,7 @@ struct LeafArgs {
 float g_scale(const qmc_integrand &f, int mode);
 
 struct LeafOut {
-  double *partial;     // kModeSum / kModeGrad: [nr][gx][tct] FP64 sums of g
+  double *partial;     // kModeSum / kModeGrad: [nr][gx][gy] FP64 sums of g, one per workgroup
   float *ppart;        // kModePoint: [nr][tct][N] per-point sums over a column tile
   float *Y;            // kModeStoreY
   int64_t ldy;
@@ -148,11 +151,12 @@ struct LeafOut {
 
 struct LeafPlan {
   int gx;              // workgroups along the subtree axis
-  int gy;              // workgroups along the column-tile axis (one tile each)
-  int spw;             // subtrees per wave
+  int gy;              // workgroups along the column axis (64 cpl columns each)
+  int spw;             // subtrees per wave (before the one-round choice)
   int nw;              // waves per workgroup
+  int cpl;             // columns of A per lane (the workgroup's tile is 64 cpl columns)
 };
-LeafPlan leaf_plan(const Geometry &G, int t, int nr, int mode);
+LeafPlan leaf_plan(const Geometry &G, int t, int nr, int mode, int gf);
 
 hipError_t launch_leaf(const Geometry &G, int mode, const qmc_integrand &f, const float *tables,
                        const float *U, int nr, int r0, const float *A, int t, int64_t lda,
