@@ -33,6 +33,7 @@ import numpy as np  # noqa: E402
 VALU_SLOTS_PER_S = 256 * 128 * 2.4e9
 VALU_PEAK_TFLOPS = 2 * VALU_SLOTS_PER_S / 1e12
 G_SLOTS = {0: 0, 1: 4, 2: 4}  # per evaluation of g: id; cos; exp (one transcendental)
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
 
 def leaf_traffic(config: int):
@@ -68,6 +69,124 @@ def leaf_algorithmic_slots(wl, split: int) -> float:
     return float(t * R * nlow + t * R * nsub * nup + N * t * R * (1 + G_SLOTS[wl.g]))
 
 
+def matvec_leaf_bytes(wl, pts) -> float:
+    """Algorithmic HBM bytes of the matvec leaf pass for one randomisation: Y
+    written once (N t 4 B), the subtree records, the upper-level rows U and the
+    lower rows of A read once each."""
+    m, t, N = wl.m, wl.t, wl.N
+    split = pts.split_level
+    lev = np.minimum(wl.w, m)
+    nsub = 2 ** (m - split)
+    rec = sum(2 ** (split - int(I)) for I in lev if I < split)
+    urows = sum(2 ** (m - int(I)) for I in sorted({int(I) for I in lev if I >= split}))
+    jlow = int(sum(1 for I in lev if I < split))
+    ldu = -(-t // 64) * 64
+    return float(4 * (N * t + nsub * rec + urows * ldu + jlow * t))
+
+
+def bench_matvec(args, wl) -> int:
+    """Y = X A for one randomisation per step, stored in HBM (the stored-Y form of
+    the method): the leaf pass streams N x t FP32 values out."""
+    import torch
+
+    import paper_2305_11645_amd as q
+    from paper_2305_11645_amd import inputs as I
+
+    prec = wl.prec if args.prec is None else args.prec
+    pts = q.Points.from_workload(wl)
+    A = torch.from_numpy(wl.A).cuda()
+    Y = torch.empty((wl.N, wl.t), dtype=torch.float32, device="cuda")
+    ws = pts.workspace(0, wl.t, None, prec)
+    stream = torch.cuda.current_stream()
+    state = {"i": 0}
+
+    def step():
+        q.reduced_matvec(pts, A, r=state["i"] % wl.R, prec=prec, Y=Y, workspace=ws)
+        state["i"] += 1
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+
+    q.timing.reset()
+    q.timing.enable(True)
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    q.timing.enable(False)
+    kern = {}
+    for name in ("tables", "levels", "leaf"):
+        tot, n = q.timing.read(name)
+        if n:
+            kern[name] = {"avg_ms": tot / n, "launches": n}
+    q.timing.reset()
+
+    ybytes = 4.0 * wl.N * wl.t
+    value = ybytes / (ms * 1e-3) / 1e9
+    leaf_ms = kern.get("leaf", {}).get("avg_ms", float("nan"))
+    lbytes = matvec_leaf_bytes(wl, pts)
+    achieved = lbytes / (leaf_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": "leaf_kernel (matvec mode)", "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None, "avg_ms": round(leaf_ms, 5), "algorithmic_bytes": lbytes}
+
+    # accuracy gate and CPU baseline on a column sample: the FP64 oracle
+    rel_err = None
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        r = (state["i"] - 1) % wl.R  # the shift of the last step
+        Yg = Y.cpu().numpy()
+        k = min(wl.t, 8)
+        t0 = time.perf_counter()
+        Yo = O.reduced_matvec(wl, r, A=wl.A[:, :k])
+        one = time.perf_counter() - t0
+        budget = 20.0
+        k2 = int(max(k, min(wl.t, k * budget / max(one, 1e-9))))
+        if k2 > k:
+            t0 = time.perf_counter()
+            Yo = O.reduced_matvec(wl, r, A=wl.A[:, :k2])
+            one = time.perf_counter() - t0
+            k = k2
+        rel_err = float(np.max(np.abs(Yg[:, :k] - Yo)) / max(np.max(np.abs(Yo)), 1e-300))
+        full = one * wl.t / k
+        cpu = {"value": round(ybytes / full / 1e9, 4), "unit": "GB/s", "cores": O.num_threads(),
+               "kind": "oracle", "seconds": round(one, 3),
+               "sample": f"{k} of {wl.t} columns of Y for one randomisation, FP64 Algorithm 1 with "
+                         f"point tables, scaled to all columns"}
+
+    out = {
+        "metric": "effective Y bandwidth GB/s (N*t*4 bytes of Y = X A per randomisation / time), reduced matvec",
+        "value": round(value, 1),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec == I.FP32 else "bf16x3",
+        "data": "synthetic (seeded generators and shifts, random A)",
+        "config": {"workload": wl.name + " (matvec)", "N": wl.N, "s": wl.s, "t": wl.t,
+                   "split_level": pts.split_level,
+                   "effective_gflops": round(2.0 * wl.N * wl.s * wl.t / (ms * 1e-3) / 1e9, 1)},
+        "rel_err_vs_oracle": rel_err,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "kernels": kern,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -79,6 +198,8 @@ def main() -> int:
     ap.add_argument("--no-dense", action="store_true")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="after timing, run one plain device copy of this many MiB (counter calibration)")
+    ap.add_argument("--op", choices=("estimate", "matvec"), default="estimate",
+                    help="estimate: Q for every randomisation (default); matvec: Y = X A stored in HBM")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -92,6 +213,8 @@ def main() -> int:
 
     torch.cuda.set_device(0)
     wl = I.make_config(args.config)
+    if args.op == "matvec":
+        return bench_matvec(args, wl)
     prec = wl.prec if args.prec is None else args.prec
     f = q.Integrand_.of(wl)
     pts = q.Points.from_workload(wl)

@@ -41,13 +41,21 @@ struct GemmProb {
   int64_t c_off, c_chunk;     // C(i,j) = Cbase[c_off + chunk*c_chunk + i*ldc + j]
 };
 
+constexpr int kMaxGemmProbs = 32;  // >= kMaxLevels: the tile table is read in whole batches
+
 struct GemmArgs {
+  int32_t tile0[kMaxGemmProbs];  // first flat tile of each problem (unused entries: INT_MAX)
   int32_t nprob, total_tiles;
   float oscale;               // C = oscale * A B
   int64_t a_rs, b_rs, c_rs;   // per-shift strides of the three bases
   int64_t ldb, ldc;
   GemmProb p[kMaxLevels];
 };
+static_assert(kMaxGemmProbs >= kMaxLevels, "tile table too short");
+
+static void finish_tile_table(GemmArgs &a) {
+  for (int q = 0; q < kMaxGemmProbs; ++q) a.tile0[q] = q < a.nprob ? a.p[q].tile0 : 0x7fffffff;
+}
 
 // Operand tile coordinates of element q of this thread: A as (i, k), B as (k, j).
 template <bool TA>
@@ -84,9 +92,12 @@ __global__ __launch_bounds__(256) void levels_gemm(GemmArgs g, const float *__re
   __shared__ float Bs[BK * BPAD];
   const int r = blockIdx.y;
   int tile = blockIdx.x;
+  // problem of this tile: the tile table is contiguous, so its scalar loads
+  // are issued together (one round trip) and scanned in registers
   int pi = 0;
-  for (int q = 1; q < g.nprob; ++q)
-    if (tile >= g.p[q].tile0) pi = q;
+#pragma unroll
+  for (int q = 1; q < kMaxGemmProbs; ++q)
+    if (tile >= g.tile0[q]) pi = q;
   const GemmProb &P = g.p[pi];
   tile -= P.tile0;
   const int chunk = tile % P.kchunks;
@@ -224,6 +235,7 @@ hipError_t launch_levels(const Geometry &G, int prec, const float *tables, int n
     tiles += P.tiles_m * P.tiles_n;
   }
   a.total_tiles = tiles;
+  finish_tile_table(a);
   return run_gemm<false>(a, prec, nr, tables, A, U, st);
 }
 
@@ -279,6 +291,7 @@ hipError_t launch_levels_adj(const Geometry &G, int prec, const float *tables, i
     tiles += P.tiles_m * P.tiles_n * P.kchunks;
   }
   a.total_tiles = tiles;
+  finish_tile_table(a);
   return run_gemm<true>(a, prec, nr, tables, S, part, st);
 }
 
