@@ -36,11 +36,12 @@ G_SLOTS = {0: 0, 1: 4, 2: 4}  # per evaluation of g: id; cos; exp (one transcend
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
 
-def leaf_traffic(config: int):
+def leaf_traffic(config: int, op: str = "estimate"):
     """HBM bytes per leaf-kernel launch from the committed counter summary of this
     workload, or None when there is none or the kernel source changed since."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"leaf_kernel_C{config}_counters.md")
+    name = f"leaf_kernel_C{config}_counters.md" if op == "estimate" else f"leaf_kernel_{op}_C{config}_counters.md"
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     fields = {}
@@ -67,6 +68,21 @@ def leaf_algorithmic_slots(wl, split: int) -> float:
     nup = len({int(I) for I in lev if I >= split})
     nsub = 2 ** (m - split)
     return float(t * R * nlow + t * R * nsub * nup + N * t * R * (1 + G_SLOTS[wl.g]))
+
+
+def calibrate_copy(mib: int) -> None:
+    """One plain device-to-device copy of `mib` MiB after the timed work: the
+    reference dispatch for scaling the HBM traffic counters."""
+    if not mib:
+        return
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
 
 
 def matvec_leaf_bytes(wl, pts) -> float:
@@ -135,7 +151,8 @@ def bench_matvec(args, wl) -> int:
     achieved = lbytes / (leaf_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": "leaf_kernel (matvec mode)", "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None, "avg_ms": round(leaf_ms, 5), "algorithmic_bytes": lbytes}
+                "traffic": leaf_traffic(args.config, "matvec"), "avg_ms": round(leaf_ms, 5),
+                "algorithmic_bytes": lbytes}
 
     # accuracy gate and CPU baseline on a column sample: the FP64 oracle
     rel_err = None
@@ -183,6 +200,7 @@ def bench_matvec(args, wl) -> int:
         "cpu_baseline": cpu,
         "kernels": kern,
     }
+    calibrate_copy(args.calibrate_copy_mib)
     print(json.dumps(out), flush=True)
     return 0
 
@@ -318,14 +336,7 @@ def main() -> int:
                  "rel_diff_vs_reduced": float(np.max(np.abs(Qd.cpu().numpy() - Qg) / np.abs(Qg)))}
         del X
 
-    if args.calibrate_copy_mib:
-        n = args.calibrate_copy_mib * (1 << 20) // 4
-        src = torch.ones(n, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+    calibrate_copy(args.calibrate_copy_mib)
 
     out = {
         "metric": "effective GFLOP/s (2*N*s*t*R/time), reduced QMC estimate vs dense X*A, rel err <= 1e-6",
