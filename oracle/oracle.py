@@ -35,7 +35,7 @@ class _Spec(ct.Structure):
                 ("w", ct.POINTER(ct.c_int32)), ("gen", ct.POINTER(ct.c_uint64)),
                 ("rand", ct.c_int32), ("R", ct.c_int32),
                 ("shift", ct.POINTER(ct.c_double)), ("dshift", ct.POINTER(ct.c_uint64)),
-                ("map", ct.c_int32)]
+                ("map", ct.c_int32), ("samples", ct.POINTER(ct.c_double))]
 
 
 class _Integrand(ct.Structure):
@@ -80,6 +80,8 @@ class Spec:
         self.gen = np.ascontiguousarray(wl.gen, dtype=np.uint64)
         self.shift = None if wl.shift is None else np.ascontiguousarray(wl.shift, dtype=np.float64)
         self.dshift = None if wl.dshift is None else np.ascontiguousarray(wl.dshift, dtype=np.uint64)
+        samples = getattr(wl, "samples", None)
+        self.samples = None if samples is None else np.ascontiguousarray(samples, dtype=np.float64)
         self.R = wl.R
         self.m, self.s = wl.m, wl.s
         self.c = _Spec(kind=wl.kind, m=wl.m, s=wl.s,
@@ -89,7 +91,8 @@ class Spec:
                        shift=None if self.shift is None else _dp(self.shift),
                        dshift=None if self.dshift is None else
                        self.dshift.ctypes.data_as(ct.POINTER(ct.c_uint64)),
-                       map=wl.map)
+                       map=wl.map,
+                       samples=None if self.samples is None else _dp(self.samples))
 
 
 def _A64(wl):

@@ -18,7 +18,10 @@
  *                (maps applied component-wise to the repeated values),
  *   product      Algorithm 1 (fast reduced matrix product), the dense product
  *                X A of eq. QMC_matrix,
- *   estimate     eq. QMC-rule, Q_N(f) = N^{-1} sum_k f(x_k^T A).
+ *   estimate     eq. QMC-rule, Q_N(f) = N^{-1} sum_k f(x_k^T A),
+ *   reduced MC   Sec. 4, eq. randpts: coordinate j draws N_j i.i.d. samples
+ *                and point n uses the one selected by the mixed-radix digits
+ *                of n (the samples are inputs, drawn by the caller).
  *
  * Readings where the paper is silent (all listed in the design notes):
  *   - the digital shift XORs the first 52 base-2 digits with a 52-bit integer
@@ -45,7 +48,7 @@
 #include <omp.h>
 #endif
 
-enum { QO_LATTICE = 0, QO_POLY_LATTICE = 1, QO_DIGITAL_NET = 2 };
+enum { QO_LATTICE = 0, QO_POLY_LATTICE = 1, QO_DIGITAL_NET = 2, QO_IID = 3 };
 enum { QO_NO_SHIFT = 0, QO_RANDOM_SHIFT = 1, QO_DIGITAL_SHIFT = 2 };
 enum { QO_MAP_ID = 0, QO_MAP_CENTER = 1, QO_MAP_INVNORM = 2, QO_MAP_TENT = 3 };
 enum { QO_G_ID = 0, QO_G_COS = 1, QO_G_EXP = 2 };
@@ -60,6 +63,7 @@ typedef struct {
     const double *shift;      /* [R*s] random shifts in [0,1) */
     const uint64_t *dshift;   /* [R*s] digital shifts, 52-bit integers */
     int32_t map;
+    const double *samples;    /* QO_IID: [R][sum_j n_j] uniforms, coordinate blocks contiguous */
 } qo_spec;
 
 typedef struct {
@@ -133,6 +137,16 @@ double qo_invnorm(double p) {
     return q < 0 ? -v : v;
 }
 
+/* The component map (Sec. 2.3; tent map of Sec. 1.2). */
+static double apply_map(const qo_spec *sp, double x) {
+    switch (sp->map) {
+        case QO_MAP_CENTER: return x - 0.5;
+        case QO_MAP_INVNORM: return qo_invnorm(x);
+        case QO_MAP_TENT: return 1.0 - fabs(1.0 - 2.0 * x);
+        default: return x;
+    }
+}
+
 /* Shift then map one coordinate value given as the integer c of c / 2^nb. */
 static double shift_and_map(const qo_spec *sp, int r, int j, uint64_t c, int nb) {
     double x;
@@ -146,12 +160,41 @@ static double shift_and_map(const qo_spec *sp, int r, int j, uint64_t c, int nb)
             if (x >= 1.0) x = x - 1.0;                       /* exact */
         }
     }
-    switch (sp->map) {
-        case QO_MAP_CENTER: return x - 0.5;
-        case QO_MAP_INVNORM: return qo_invnorm(x);
-        case QO_MAP_TENT: return 1.0 - fabs(1.0 - 2.0 * x);
-        default: return x;
+    return apply_map(sp, x);
+}
+
+/* ------------------------------------------------------------ reduced Monte Carlo
+ *
+ * Sec. 4: with N_j = b^{m - w_j} (capped at m), N_{s+1} = 1 and
+ * M_j = N_j / N_{j+1}, every n < N is n = sum_i m_i N_{i+1} with 0 <= m_i < M_i,
+ * and eq. randpts gives coordinate j of point n the sample with index
+ * sum_{i >= j} m_i N_{i+1} among the N_j i.i.d. samples of that coordinate.
+ * Indices below are 0-based (the paper's j is j + 1 here).
+ */
+static int64_t iid_offset(const qo_spec *sp, int j) {   /* start of coordinate j's samples */
+    int64_t off = 0;
+    for (int i = 0; i < j; ++i) off += (int64_t)1 << nbits_of(sp, i);
+    return off;
+}
+
+static uint64_t iid_N(const qo_spec *sp, int i) {       /* N_i, and N_s = 1 past the last */
+    return i >= sp->s ? 1 : (UINT64_C(1) << nbits_of(sp, i));
+}
+
+static uint64_t iid_index(const qo_spec *sp, int j, uint64_t n) {
+    uint64_t idx = 0;
+    for (int i = sp->s - 1; i >= j; --i) {
+        uint64_t weight = iid_N(sp, i + 1);               /* N_{i+1} */
+        uint64_t M = iid_N(sp, i) / weight;                /* M_i */
+        uint64_t digit = (n / weight) % M;                 /* m_i */
+        idx += digit * weight;
     }
+    return idx;
+}
+
+static double iid_value(const qo_spec *sp, int r, int j, uint64_t index) {
+    const double *y = sp->samples + (size_t)r * iid_offset(sp, sp->s) + iid_offset(sp, j);
+    return apply_map(sp, y[index]);
 }
 
 /* ------------------------------------------------------------ point sets */
@@ -182,7 +225,8 @@ int qo_point_values(const qo_spec *sp, int r, int j, double *out) {
     int nb = nbits_of(sp, j);
     uint64_t n = UINT64_C(1) << nb;
     for (uint64_t rho = 0; rho < n; ++rho)
-        out[rho] = shift_and_map(sp, r, j, reduced_int(sp, j, rho), nb);
+        out[rho] = sp->kind == QO_IID ? iid_value(sp, r, j, rho)
+                                      : shift_and_map(sp, r, j, reduced_int(sp, j, rho), nb);
     return 0;
 }
 
@@ -224,6 +268,10 @@ int qo_point_matrix_unreduced(const qo_spec *sp, int r, double *X) {
 #pragma omp parallel for schedule(static)
     for (int64_t k = 0; k < N; ++k) {
         for (int j = 0; j < s; ++j) {
+            if (sp->kind == QO_IID) {   /* eq. randpts, digit by digit */
+                X[k * s + j] = iid_value(sp, r, j, iid_index(sp, j, (uint64_t)k));
+                continue;
+            }
             uint64_t cN = unreduced_int_over_N(sp, j, (uint64_t)k);
             /* value cN / 2^m; shift_and_map takes c / 2^nb, so pass nb = m */
             X[k * s + j] = shift_and_map(sp, r, j, cN, sp->m);
@@ -248,7 +296,12 @@ int qo_dense_matvec(const double *X, int64_t N, int s, const double *A, int t, d
 
 /* a coordinate whose every value is exactly zero contributes nothing (j > s*) */
 static int column_is_zero(const qo_spec *sp, int j) {
-    return sp->w[j] >= sp->m && sp->rand == QO_NO_SHIFT && sp->map == QO_MAP_ID;
+    return sp->kind != QO_IID && sp->w[j] >= sp->m && sp->rand == QO_NO_SHIFT && sp->map == QO_MAP_ID;
+}
+
+/* randomisations (shifts) or, for reduced Monte Carlo, independent replicates */
+static int replicates(const qo_spec *sp) {
+    return sp->kind == QO_IID || sp->rand != QO_NO_SHIFT ? sp->R : 1;
 }
 
 /*
@@ -355,7 +408,7 @@ int qo_estimate(const qo_spec *sp, const double *A, int t, const qo_integrand *f
     double *P = (double *)malloc(sizeof(double) * (size_t)N * tb);
     double *u = (double *)malloc(sizeof(double) * (size_t)N);
     if (!P || !u) { free(P); free(u); return 1; }
-    int R = sp->rand == QO_NO_SHIFT ? 1 : sp->R;
+    int R = replicates(sp);
     for (int r = 0; r < R; ++r) {
         if (point_means(sp, r, A, t, f, u, P, nmadd)) { free(P); free(u); return 1; }
         for (int64_t k = 0; k < N; ++k) u[k] = h_val(f, u[k]);
@@ -382,7 +435,7 @@ int qo_estimate_grad(const qo_spec *sp, const double *A, int t, const qo_integra
     double *hv = (double *)malloc(sizeof(double) * (size_t)N);
     double *v = (double *)malloc(sizeof(double) * (size_t)N);
     if (!P || !u || !hv || !v) { free(P); free(u); free(hv); free(v); return 1; }
-    int R = sp->rand == QO_NO_SHIFT ? 1 : sp->R;
+    int R = replicates(sp);
     for (int r = 0; r < R; ++r) {
         if (point_means(sp, r, A, t, f, u, P, NULL)) { free(P); free(u); free(hv); free(v); return 1; }
         for (int64_t k = 0; k < N; ++k) hv[k] = h_val(f, u[k]);

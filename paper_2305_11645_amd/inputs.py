@@ -12,8 +12,9 @@ applications (Section 1: Gaussian expectations through a factor of the
 covariance, and PDE coefficients written as x^T A).  Indices are 0-based here,
 so the paper's w_j = floor(log2 j) for j = 1..s becomes floor(log2(j+1)).
 
-Draw order per workload: generators, then A, then shifts, all from
-``numpy.random.default_rng(seed)`` with ``seed = 1000 + c`` by default.
+Draw order per workload: generators, then A, then shifts (or, for reduced
+Monte Carlo, the i.i.d. samples), all from ``numpy.random.default_rng(seed)``
+with ``seed = 1000 + c`` by default.
 """
 from __future__ import annotations
 
@@ -23,7 +24,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 # enum values shared by convention with include/qmcred.h (plain integers)
-LATTICE, POLY_LATTICE, DIGITAL_NET = 0, 1, 2
+LATTICE, POLY_LATTICE, DIGITAL_NET, IID = 0, 1, 2, 3
 NO_SHIFT, RANDOM_SHIFT, DIGITAL_SHIFT = 0, 1, 2
 MAP_ID, MAP_CENTER, MAP_INVNORM, MAP_TENT = 0, 1, 2, 3
 G_ID, G_COS, G_EXP = 0, 1, 2
@@ -54,6 +55,7 @@ class Workload:
     h: int
     K: float
     prec: int = FP32
+    samples: np.ndarray | None = None  # float64 [R, sum_j n_j] in (0, 1)    (kind IID)
     extra: dict = field(default_factory=dict)
 
     @property
@@ -126,6 +128,23 @@ def draw_net_lower(rng: np.random.Generator, s: int, m: int) -> np.ndarray:
     return words
 
 
+def draw_iid_samples(rng: np.random.Generator, R: int, nb: np.ndarray) -> np.ndarray:
+    """Reduced Monte Carlo inputs: for each of R replicates and each coordinate j,
+    2^nb_j independent uniforms, coordinate blocks contiguous: [R, sum_j 2^nb_j].
+    Each value is (k + 1/2) 2^-53 with k uniform below 2^53: exact in FP64 and
+    strictly inside (0, 1), so the inverse-normal map is always finite."""
+    total = int(sum(1 << int(n) for n in nb))
+    k = rng.integers(0, 1 << 53, size=(R, total), dtype=np.uint64)
+    return (k.astype(np.float64) + 0.5) * 2.0 ** -53
+
+
+def tridiag_cholesky_T(s: int, diag: float = 0.4, off: float = 0.2) -> np.ndarray:
+    """A = L^T with L L^T = Sigma, Sigma tridiagonal Toeplitz (diag on the
+    diagonal, off next to it): the basket-option covariance of Section 5."""
+    Sig = np.diag(np.full(s, diag)) + np.diag(np.full(s - 1, off), 1) + np.diag(np.full(s - 1, off), -1)
+    return np.ascontiguousarray(np.linalg.cholesky(Sig).T)
+
+
 # ---------------------------------------------------------------- A matrices
 
 def exp_kernel_cholesky_T(n: int, ell: float = 0.1) -> np.ndarray:
@@ -151,12 +170,20 @@ CONFIG_NAMES = {
     3: "C3 digitally shifted reduced net m=20 s=t=1024 Gaussian call",
     4: "C4 KL coefficients reduced lattice m=18 s=2048 t=4096 R=32 exp-mean",
     5: "C5 shifted reduced lattice m=20 s=t=1024 cos-mean gradient",
+    6: "C6 reduced Monte Carlo basket call m=20 s=t=512 R=4",
 }
+
+# Basket option of Section 5 (Black-Scholes, zero rate): S_j(0) = 100, T = 1,
+# strike 110, Sigma_jj = 0.4.  S_j(T) = 100 exp(-0.2 + y_j), so the payoff is
+# BASKET_SCALE * max(0, mean_j exp(y_j) - BASKET_K): the library's estimate
+# times BASKET_SCALE is the option price.
+BASKET_SCALE = 100.0 * math.exp(-0.2)
+BASKET_K = 110.0 / BASKET_SCALE
 
 
 def make_config(c: int, seed: int | None = None, *, m: int | None = None, s: int | None = None,
                 t: int | None = None, R: int | None = None, kind: int | None = None) -> Workload:
-    """Build workload C<c> (1..5).  Size overrides give the same recipe at other shapes."""
+    """Build workload C<c> (1..6).  Size overrides give the same recipe at other shapes."""
     if seed is None:
         seed = 1000 + c
     rng = np.random.default_rng(seed)
@@ -207,6 +234,17 @@ def make_config(c: int, seed: int | None = None, *, m: int | None = None, s: int
         g, cc, h, K = G_COS, 1.0, H_ID, 0.0
         A_fn = lambda: rng.standard_normal((s_, t_)) / math.sqrt(s_)
         prec = FP32
+    elif c == 6:
+        m_, s_, t_, R_ = 20, 512, 512, 4
+        m_, s_, t_, R_ = m or m_, s or s_, t or t_, R or R_
+        w = w_log2(s_, max(m_ - 4, 0))
+        kind_ = IID
+        rand, mp = NO_SHIFT, MAP_INVNORM
+        g, cc, h, K = G_EXP, 1.0, H_CALL, BASKET_K
+        if s_ != t_:
+            raise ValueError("C6 uses a square Cholesky factor: s must equal t")
+        A_fn = lambda: tridiag_cholesky_T(s_)
+        prec = FP32
     else:
         raise ValueError(f"unknown workload C{c}")
 
@@ -217,11 +255,15 @@ def make_config(c: int, seed: int | None = None, *, m: int | None = None, s: int
         gen = draw_poly(rng, nb)
     elif kind_ == DIGITAL_NET:
         gen = draw_net_lower(rng, s_, m_)
+    elif kind_ == IID:
+        gen = np.ones(s_, dtype=np.uint64)  # unused
     else:
         raise ValueError("kind")
     A64 = np.ascontiguousarray(A_fn(), dtype=np.float64)
-    shift = dshift = None
-    if rand == RANDOM_SHIFT:
+    shift = dshift = samples = None
+    if kind_ == IID:
+        samples = draw_iid_samples(rng, R_, nb)
+    elif rand == RANDOM_SHIFT:
         shift = rng.random((R_, s_))
     elif rand == DIGITAL_SHIFT:
         dshift = rng.integers(0, 1 << 52, size=(R_, s_), dtype=np.uint64)
@@ -229,7 +271,7 @@ def make_config(c: int, seed: int | None = None, *, m: int | None = None, s: int
         R_ = 1
     return Workload(name=CONFIG_NAMES[c], kind=kind_, b=2, m=m_, s=s_, t=t_, w=w,
                     gen=gen, rand=rand, R=R_, shift=shift, dshift=dshift, map=mp,
-                    A64=A64, g=g, c=cc, h=h, K=K, prec=prec)
+                    A64=A64, g=g, c=cc, h=h, K=K, prec=prec, samples=samples)
 
 
 def make_custom(*, kind: int, m: int, s: int, t: int, w: np.ndarray, rand: int = NO_SHIFT,
@@ -243,11 +285,17 @@ def make_custom(*, kind: int, m: int, s: int, t: int, w: np.ndarray, rand: int =
         gen = draw_lattice(rng, nb)
     elif kind == POLY_LATTICE:
         gen = draw_poly(rng, nb)
+    elif kind == IID:
+        gen = np.ones(s, dtype=np.uint64)  # unused
     else:
         gen = draw_net_lower(rng, s, m)
     A64 = rng.standard_normal((s, t)) * A_scale
-    shift = dshift = None
-    if rand == RANDOM_SHIFT:
+    shift = dshift = samples = None
+    if kind == IID:
+        if rand != NO_SHIFT:
+            raise ValueError("reduced Monte Carlo takes no shift: R counts independent replicates")
+        samples = draw_iid_samples(rng, R, nb)
+    elif rand == RANDOM_SHIFT:
         shift = rng.random((R, s))
     elif rand == DIGITAL_SHIFT:
         dshift = rng.integers(0, 1 << 52, size=(R, s), dtype=np.uint64)
@@ -255,4 +303,4 @@ def make_custom(*, kind: int, m: int, s: int, t: int, w: np.ndarray, rand: int =
         R = 1
     return Workload(name="custom", kind=kind, b=2, m=m, s=s, t=t, w=w, gen=gen, rand=rand,
                     R=R, shift=shift, dshift=dshift, map=map, A64=np.ascontiguousarray(A64),
-                    g=g, c=c, h=h, K=K)
+                    g=g, c=c, h=h, K=K, samples=samples)

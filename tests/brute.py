@@ -8,6 +8,8 @@ Used to pin the oracle's point tables.
   polynomial   Sec. 1.1: x_k = nu(k(x) g_j(x) / x^m), g_j = x^{w_j} g'_j
   digital net  eq. def:digital with the reduced matrices of eq.
                reduced_genmat_net2: last min(w_j, m) rows of C^{(j)} set to 0
+  reduced MC   Sec. 4, eq. randpts: the mixed-radix digits of n select the
+               sample of each coordinate (greedy from the top digit down)
 """
 from __future__ import annotations
 
@@ -16,7 +18,7 @@ from fractions import Fraction
 import numpy as np
 from scipy.special import ndtri
 
-from paper_2305_11645_amd.inputs import (DIGITAL_NET, DIGITAL_SHIFT, LATTICE, MAP_CENTER,
+from paper_2305_11645_amd.inputs import (DIGITAL_NET, DIGITAL_SHIFT, IID, LATTICE, MAP_CENTER,
                                          MAP_INVNORM, MAP_TENT, POLY_LATTICE, RANDOM_SHIFT)
 
 
@@ -81,13 +83,30 @@ def digital_shift(x: Fraction, delta: int) -> float:
     return float(val + Fraction(1, 2 ** 53))
 
 
+def randpts_index(wl, n: int, j: int) -> int:
+    """eq. randpts: with N_i = 2^{m - min(w_i, m)}, N_{s+1} = 1, write
+    n = m_1 N_2 + m_2 N_3 + ... + m_s N_{s+1} (0 <= m_i < N_i / N_{i+1}, top
+    digit first); coordinate j takes sample m_j N_{j+1} + ... + m_s N_{s+1}."""
+    m, s = wl.m, wl.s
+    Nn = [1 << (m - min(int(wl.w[i]), m)) for i in range(s)] + [1]
+    rest, dig = n, []
+    for i in range(s):
+        dig.append(rest // Nn[i + 1])
+        rest -= dig[-1] * Nn[i + 1]
+    assert rest == 0 and all(0 <= dig[i] < Nn[i] // Nn[i + 1] for i in range(s))
+    return sum(dig[i] * Nn[i + 1] for i in range(j, s))
+
+
 def value(wl, r: int, k: int, j: int) -> float:
     """Point k, coordinate j, shift r, after the map (FP64)."""
-    x = unshifted_value(wl, k, j)
-    if wl.rand == DIGITAL_SHIFT:
-        v = digital_shift(x, int(wl.dshift[r, j]))
+    if wl.kind == IID:
+        nb = [wl.m - min(int(wl.w[i]), wl.m) for i in range(wl.s)]
+        off = sum(1 << nb[i] for i in range(j))
+        v = float(wl.samples[r, off + randpts_index(wl, k, j)])
+    elif wl.rand == DIGITAL_SHIFT:
+        v = digital_shift(unshifted_value(wl, k, j), int(wl.dshift[r, j]))
     else:
-        v = float(x)
+        v = float(unshifted_value(wl, k, j))
         if wl.rand == RANDOM_SHIFT:
             v = v + float(wl.shift[r, j])
             if v >= 1.0:

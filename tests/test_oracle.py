@@ -339,3 +339,146 @@ def test_gradient_matches_closed_form_derivative(oracle_lib):
     # Frobenius error within 4 standard errors of the shift average, and small
     assert np.linalg.norm(est - ref) <= 4 * np.sqrt(np.sum(se ** 2))
     assert np.linalg.norm(est - ref) <= 1e-2 * np.linalg.norm(ref)
+
+
+# ------------------------------------------------------------------ reduced Monte Carlo (Sec. 4)
+
+def iid_small(m=6, s=9, t=3, R=2, w=None, mp=I.MAP_ID, g=I.G_COS, h=I.H_ID, K=0.0, c=1.0, seed=5,
+              A_scale=1.0):
+    if w is None:
+        w = I.w_log2(s, m + 1)  # includes coordinates with w_j >= m (one sample)
+    return I.make_custom(kind=I.IID, m=m, s=s, t=t, w=w, rand=I.NO_SHIFT, R=R, map=mp, g=g, h=h, K=K,
+                         c=c, seed=seed, A_scale=A_scale)
+
+
+@pytest.mark.parametrize("mp", [I.MAP_ID, I.MAP_CENTER, I.MAP_TENT, I.MAP_INVNORM])
+def test_iid_tables_follow_randpts(oracle_lib, mp):
+    """Sec. 4, eq. randpts: the mixed-radix digits of n select coordinate j's
+    sample.  The oracle's per-coordinate tables indexed by n mod N_j, and its own
+    unreduced point matrix, equal the brute-force points built digit by digit
+    (top digit first; the oracle decomposes bottom-up)."""
+    O = oracle_lib
+    wl = iid_small(mp=mp, m=6, s=12, R=2)
+    for r in range(wl.R):
+        X = brute.point_matrix(wl, r)
+        Xo = O.point_matrix_unreduced(wl, r)
+        k = np.arange(wl.N)
+        for j in range(wl.s):
+            vals = O.point_values(wl, r, j)
+            assert len(vals) == 2 ** (wl.m - min(int(wl.w[j]), wl.m))
+            if mp == I.MAP_INVNORM:  # AS241 (oracle) vs scipy's ndtri (brute force)
+                np.testing.assert_allclose(vals[k % len(vals)], X[:, j], rtol=1e-13, atol=1e-13)
+                np.testing.assert_allclose(Xo[:, j], X[:, j], rtol=1e-13, atol=1e-13)
+            else:
+                np.testing.assert_array_equal(vals[k % len(vals)], X[:, j])
+                np.testing.assert_array_equal(Xo[:, j], X[:, j])
+
+
+def test_iid_algorithm1_matches_dense(oracle_lib):
+    """Sec. 4.1: the recursive computation of z_{j,.} equals the dense product
+    of the (repeated-sample) point matrix with A."""
+    O = oracle_lib
+    wl = iid_small(m=7, s=14, t=6, R=2, mp=I.MAP_INVNORM)
+    A = wl.A.astype(np.float64)
+    for r in range(wl.R):
+        Y = O.reduced_matvec(wl, r)
+        Yd = O.point_matrix_unreduced(wl, r) @ A
+        assert np.linalg.norm(Y - Yd) <= 1e-13 * np.linalg.norm(Yd)
+
+
+def theorem5_variance(mu_tail, mu_empty, Nj):
+    """Theorem 5: Var Q = sum_{k=1}^s mu_{k..s} prod_{j=k}^s M_j^-1 (1 - 1/M_{k-1})
+    - mu_empty / M_s, with M_j = N_j / N_{j+1}, N_{s+1} = 1 and 1 - 1/M_0 := 1.
+    mu_tail[k-1] is mu_{k..s} (1-based k)."""
+    s = len(Nj)
+    Nn = [float(x) for x in Nj] + [1.0]
+    M = [Nn[i] / Nn[i + 1] for i in range(s)]
+    var = 0.0
+    for k in range(1, s + 1):
+        prod = 1.0
+        for j in range(k, s + 1):
+            prod /= M[j - 1]
+        var += mu_tail[k - 1] * prod * (1.0 if k == 1 else 1.0 - 1.0 / M[k - 2])
+    return var - mu_empty / M[s - 1]
+
+
+def test_theorem5_linear_integrand_identity():
+    """For f(x) = sum_j c_j x_j on U[0,1)^s, mu_u = mu_empty + sum_{j in u} c_j^2 / 12,
+    and the coordinate means are averages of N_j independent uniforms, so the
+    variance is sum_j c_j^2 / (12 N_j).  Theorem 5 must give exactly that."""
+    rng = np.random.default_rng(11)
+    for w in ([0, 1, 1, 3, 3, 4], [0, 0, 2, 5, 6, 6, 6], [0, 2, 4, 6]):
+        m = 7
+        cj = rng.standard_normal(len(w))
+        Nj = [2 ** (m - min(x, m)) for x in w]
+        mu_empty = (cj.sum() / 2) ** 2
+        mu_tail = [mu_empty + np.sum(cj[k:] ** 2) / 12 for k in range(len(w))]
+        direct = float(np.sum(cj ** 2 / (12 * np.array(Nj, dtype=float))))
+        assert abs(theorem5_variance(mu_tail, mu_empty, Nj) - direct) <= 1e-14 * max(direct, 1.0)
+
+
+def _cos_mean_mu(A, u):
+    """mu_u of f(x) = t^-1 sum_i cos(sum_j a_ji x_j), x uniform on [0,1)^s, in
+    closed form: with phi(a) = (e^{ia}-1)/(ia), E_{x_-u} f = t^-1 sum_i
+    Re(e^{i y_u,i} Phi_i) (Phi_i = prod_{j not in u} phi(a_ji)), and
+    E[Re(e^{iA}P) Re(e^{iB}Q)] = Re[P Q Psi(a+b) + P conj(Q) Psi(a-b)] / 2,
+    Psi(b) = prod_{j in u} phi(b_j)."""
+    def phi(a):
+        a = np.asarray(a, dtype=np.complex128)
+        out = np.ones_like(a)
+        nz = np.abs(a) > 0
+        out[nz] = (np.exp(1j * a[nz]) - 1) / (1j * a[nz])
+        return out
+    s, t = A.shape
+    inu = np.zeros(s, dtype=bool)
+    inu[list(u)] = True
+    Phi = np.prod(phi(A[~inu, :]), axis=0) if (~inu).any() else np.ones(t, dtype=np.complex128)
+    Au = A[inu, :]
+    tot = 0.0
+    for i in range(t):
+        for k in range(t):
+            pp = np.prod(phi(Au[:, i] + Au[:, k])) if inu.any() else 1.0
+            pm = np.prod(phi(Au[:, i] - Au[:, k])) if inu.any() else 1.0
+            tot += 0.5 * np.real(Phi[i] * Phi[k] * pp + Phi[i] * np.conj(Phi[k]) * pm)
+    return tot / t ** 2
+
+
+def test_reduced_mc_variance_theorem5(oracle_lib):
+    """Theorem 5 against the oracle: over many independent replicates the
+    sample mean of Q is the integral (unbiased) and the sample variance is
+    Theorem 5's variance, which here is far from plain Monte Carlo's
+    (mu_{1..s} - mu_empty) / N, so a wrong sample-sharing pattern would fail."""
+    O = oracle_lib
+    m, s, t, R = 6, 6, 2, 3000
+    w = np.array([0, 1, 2, 2, 3, 4], dtype=np.int32)
+    wl = I.make_custom(kind=I.IID, m=m, s=s, t=t, w=w, rand=I.NO_SHIFT, R=R, map=I.MAP_ID,
+                       g=I.G_COS, h=I.H_ID, A_scale=2.0, seed=21)
+    A = wl.A.astype(np.float64)
+    Q, _ = O.estimate(wl)
+    mu_empty = _cos_mean_mu(A, [])
+    mu_tail = [_cos_mean_mu(A, range(k, s)) for k in range(s)]
+    Nj = [2 ** (m - int(x)) for x in w]
+    var_th = theorem5_variance(mu_tail, mu_empty, Nj)
+    var_plain = (mu_tail[0] - mu_empty) / 2 ** m
+    assert var_th > 2.0 * var_plain
+    phi = (np.exp(1j * A) - 1) / (1j * A)
+    integral = float(np.mean(np.real(np.prod(phi, axis=0))))  # E f = t^-1 sum_i Re prod_j phi(a_ji)
+    assert abs(integral ** 2 - mu_empty) <= 1e-12 * max(mu_empty, 1e-300)
+    assert abs(np.mean(Q) - integral) <= 4 * math.sqrt(var_th / R)
+    v = np.var(Q, ddof=1)
+    m4 = np.mean((Q - np.mean(Q)) ** 4)
+    se_v = math.sqrt(max(m4 - v * v, 0.0) / R)
+    assert abs(v - var_th) <= 5 * se_v, (v, var_th, se_v)
+
+
+def test_reduced_mc_gaussian_mean(oracle_lib):
+    """Normal samples through the inverse-normal map: y_i = sum_j a_ji Phi^-1(u_j)
+    is N(0, sum_j a_ji^2), so E exp(c y_i) = exp(c^2 sum_j a_ji^2 / 2) exactly;
+    the mean over independent replicates is within 4 standard errors."""
+    O = oracle_lib
+    wl = iid_small(m=8, s=16, t=4, R=64, mp=I.MAP_INVNORM, g=I.G_EXP, c=0.3, A_scale=0.3, seed=9)
+    A = wl.A.astype(np.float64)
+    Q, _ = O.estimate(wl)
+    exact = float(np.mean(np.exp(wl.c ** 2 * np.sum(A * A, axis=0) / 2)))
+    se = np.std(Q, ddof=1) / math.sqrt(wl.R)
+    assert abs(np.mean(Q) - exact) <= 4 * se
