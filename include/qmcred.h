@@ -50,11 +50,14 @@ typedef enum {
     QMC_EDEVICE = 4        /* a HIP runtime call or kernel launch failed               */
 } qmc_status;
 
-/* Point-set families (Section 1.1, Section 3). */
+/* Point-set families (Section 1.1, Section 3, Section 4). */
 typedef enum {
     QMC_LATTICE = 0,       /* reduced rank-1 lattice, Section 1.3                     */
     QMC_POLY_LATTICE = 1,  /* reduced polynomial lattice, g_j = x^{w_j} g'_j          */
-    QMC_DIGITAL_NET = 2    /* reduced digital net, eq. reduced_genmat_net2           */
+    QMC_DIGITAL_NET = 2,   /* reduced digital net, eq. reduced_genmat_net2           */
+    QMC_IID = 3            /* reduced Monte Carlo, Section 4 eq. randpts: coordinate j
+                              has n_j i.i.d. samples (caller-drawn), point k uses
+                              sample k mod n_j                                      */
 } qmc_kind;
 
 /* Randomisation (Section 1.2 random shift; base-2 digital shift). */
@@ -102,11 +105,18 @@ typedef enum { QMC_H_ID = 0, QMC_H_CALL = 1 /* max(0, u - K) */ } qmc_h;
  *                 The reduced matrix must have zero columns q > m - min(w_j,m)
  *                 (true for lower-triangular C^{(j)}); otherwise the points
  *                 are not periodic in k and QMC_EUNSUPPORTED is returned.
+ *          reduced Monte Carlo (QMC_IID): ignored (may be NULL).
  *   rand, R, shift [R*s] in [0,1) (QMC_RANDOM_SHIFT) or dshift [R*s] < 2^52
  *                 (QMC_DIGITAL_SHIFT): R independent randomisations, all
- *                 evaluated by one call.  With QMC_NO_SHIFT, R must be 1.
+ *                 evaluated by one call.  With QMC_NO_SHIFT, R must be 1,
+ *                 except for QMC_IID, where rand must be QMC_NO_SHIFT and R
+ *                 counts independent replicates.
  *   map           component map; QMC_MAP_INVNORM requires a shift because the
- *                 unshifted point x_0 = 0 (Section 2.3).
+ *                 unshifted point x_0 = 0 (Section 2.3), or QMC_IID samples.
+ *   samples       QMC_IID only: [R][sum_j n_j] uniforms in [0,1) (in (0,1)
+ *                 with QMC_MAP_INVNORM), n_j = 2^{m - min(w_j, m)}; replicate
+ *                 r holds coordinate 0's n_0 samples, then coordinate 1's, ...
+ *                 Copied to the device by qmc_points_init.
  */
 typedef struct {
     int32_t b, m, s;
@@ -118,6 +128,7 @@ typedef struct {
     const double *shift;
     const uint64_t *dshift;
     int32_t map;              /* qmc_map */
+    const double *samples;    /* QMC_IID: i.i.d. uniforms, see above */
 } qmc_point_spec;
 
 /* f(y) = h(t^-1 sum_i g(y_i)), y = x^T A in R^t.  h is applied per point. */
@@ -132,11 +143,13 @@ typedef struct qmc_points_s *qmc_points;
 
 /*
  * Create a point set on the current HIP device (Section 1.3, Section 3,
- * Algorithm 3).  Validates spec (EINVAL: b not prime, w[0] != 0, w decreasing,
- * a generator outside its allowed set, shift outside [0,1) or >= 2^52, R < 1,
- * INVNORM without a shift; EUNSUPPORTED: b != 2, m outside [1, 24], a net not
- * periodic after reduction), plans the levels and uploads generators and
- * shifts.  Synchronous.  *out owns device memory; release with qmc_points_free.
+ * Algorithm 3, Section 4).  Validates spec (EINVAL: b not prime, w[0] != 0, w
+ * decreasing, a generator outside its allowed set, shift outside [0,1) or
+ * >= 2^52, R < 1, INVNORM without a shift, QMC_IID with a shift, without
+ * samples or with a sample outside [0,1) ((0,1) under INVNORM);
+ * EUNSUPPORTED: b != 2, m outside [1, 24], a net not periodic after
+ * reduction), plans the levels and uploads generators, shifts and samples.
+ * Synchronous.  *out owns device memory; release with qmc_points_free.
  */
 qmc_status qmc_points_init(qmc_points *out, const qmc_point_spec *spec);
 

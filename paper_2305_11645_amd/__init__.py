@@ -18,7 +18,7 @@ import numpy as np
 
 from ._lib import (EXPORTS, Integrand, PointSpec, QMCDeviceError, QMCError, QMCInvalid,
                    QMCNoMemory, QMCUnsupported, check, load)
-from .inputs import (DIGITAL_NET, DIGITAL_SHIFT, FP32, G_COS, G_EXP, G_ID, H_CALL, H_ID, LATTICE,
+from .inputs import (DIGITAL_NET, DIGITAL_SHIFT, FP32, IID, G_COS, G_EXP, G_ID, H_CALL, H_ID, LATTICE,
                      MAP_CENTER, MAP_ID, MAP_INVNORM, MAP_TENT, NO_SHIFT, POLY_LATTICE,
                      RANDOM_SHIFT, SPLIT_BF16X3)
 
@@ -55,11 +55,12 @@ class Integrand_:
 class Points:
     """A reduced point set living on the current GPU (wraps qmc_points_init)."""
 
-    def __init__(self, *, kind: int, m: int, s: int, w, gen, rand: int = NO_SHIFT, R: int = 1,
-                 shift=None, dshift=None, map: int = MAP_ID, b: int = 2):
+    def __init__(self, *, kind: int, m: int, s: int, w, gen=None, rand: int = NO_SHIFT, R: int = 1,
+                 shift=None, dshift=None, map: int = MAP_ID, b: int = 2, samples=None):
         L = load()
         self._w = np.ascontiguousarray(w, dtype=np.int32)
-        self._gen = np.ascontiguousarray(gen, dtype=np.uint64)
+        self._gen = np.ascontiguousarray(np.ones(s) if gen is None else gen, dtype=np.uint64)
+        self._samples = None if samples is None else np.ascontiguousarray(samples, dtype=np.float64)
         self._shift = None if shift is None else np.ascontiguousarray(shift, dtype=np.float64)
         self._dshift = None if dshift is None else np.ascontiguousarray(dshift, dtype=np.uint64)
         spec = PointSpec(
@@ -69,7 +70,8 @@ class Points:
             rand=rand, R=R,
             shift=None if self._shift is None else self._shift.ctypes.data_as(ct.POINTER(ct.c_double)),
             dshift=None if self._dshift is None else self._dshift.ctypes.data_as(ct.POINTER(ct.c_uint64)),
-            map=map)
+            map=map,
+            samples=None if self._samples is None else self._samples.ctypes.data_as(ct.POINTER(ct.c_double)))
         h = ct.c_void_p()
         check(L.qmc_points_init(ct.byref(h), ct.byref(spec)))
         self._h = h
@@ -84,7 +86,7 @@ class Points:
     @classmethod
     def from_workload(cls, wl) -> "Points":
         return cls(kind=wl.kind, m=wl.m, s=wl.s, w=wl.w, gen=wl.gen, rand=wl.rand, R=wl.R,
-                   shift=wl.shift, dshift=wl.dshift, map=wl.map)
+                   shift=wl.shift, dshift=wl.dshift, map=wl.map, samples=getattr(wl, "samples", None))
 
     @property
     def handle(self) -> ct.c_void_p:

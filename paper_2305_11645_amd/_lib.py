@@ -27,7 +27,7 @@ class PointSpec(ct.Structure):
                 ("w", ct.POINTER(ct.c_int32)), ("gen", ct.POINTER(ct.c_uint64)),
                 ("rand", ct.c_int32), ("R", ct.c_int32),
                 ("shift", ct.POINTER(ct.c_double)), ("dshift", ct.POINTER(ct.c_uint64)),
-                ("map", ct.c_int32)]
+                ("map", ct.c_int32), ("samples", ct.POINTER(ct.c_double))]
 
 
 class Integrand(ct.Structure):

@@ -17,6 +17,7 @@ struct qmc_points_s {
   qmc::Geometry G{};
   qmc::DevSpec D{};
   void *d_gen = nullptr, *d_nb = nullptr, *d_shift = nullptr, *d_dshift = nullptr;
+  void *d_samples = nullptr, *d_soff = nullptr;
 };
 
 namespace {
@@ -299,8 +300,9 @@ qmc_status qmc_points_init(qmc_points *out, const qmc_point_spec *sp) {
   if (sp->b != 2) return fail(QMC_EUNSUPPORTED, "only b = 2 is supported (b = %d)", sp->b);
   if (sp->m < 1 || sp->m > kMaxM) return fail(QMC_EUNSUPPORTED, "m = %d outside [1, %d]", sp->m, kMaxM);
   if (sp->s < 1) return fail(QMC_EINVAL, "s = %d must be >= 1", sp->s);
-  if (sp->kind < QMC_LATTICE || sp->kind > QMC_DIGITAL_NET) return fail(QMC_EINVAL, "unknown kind %d", sp->kind);
-  if (!sp->w || !sp->gen) return fail(QMC_EINVAL, "w or gen is null");
+  if (sp->kind < QMC_LATTICE || sp->kind > QMC_IID) return fail(QMC_EINVAL, "unknown kind %d", sp->kind);
+  const bool iid = sp->kind == QMC_IID;
+  if (!sp->w || (!sp->gen && !iid)) return fail(QMC_EINVAL, "w or gen is null");
   const int m = sp->m, s = sp->s;
   if (sp->w[0] != 0) return fail(QMC_EINVAL, "w[0] = %d must be 0", sp->w[0]);
   for (int j = 1; j < s; ++j) {
@@ -323,6 +325,8 @@ qmc_status qmc_points_init(qmc_points *out, const qmc_point_spec *sp) {
         gen[(size_t)j * m + q] = (uint32_t)wd;
       }
     }
+  } else if (iid) {
+    gen.assign(s, 0u);  // reduced Monte Carlo draws no generators
   } else {
     gen.resize(s);
     for (int j = 0; j < s; ++j) {
@@ -338,7 +342,9 @@ qmc_status qmc_points_init(qmc_points *out, const qmc_point_spec *sp) {
   }
   if (sp->rand < QMC_NO_SHIFT || sp->rand > QMC_DIGITAL_SHIFT) return fail(QMC_EINVAL, "unknown randomisation %d", sp->rand);
   if (sp->R < 1) return fail(QMC_EINVAL, "R = %d must be >= 1", sp->R);
-  if (sp->rand == QMC_NO_SHIFT && sp->R != 1) return fail(QMC_EINVAL, "R must be 1 without a shift");
+  if (iid && sp->rand != QMC_NO_SHIFT)
+    return fail(QMC_EINVAL, "reduced Monte Carlo takes no shift (R counts independent replicates)");
+  if (!iid && sp->rand == QMC_NO_SHIFT && sp->R != 1) return fail(QMC_EINVAL, "R must be 1 without a shift");
   if (sp->R > 65535) return fail(QMC_EUNSUPPORTED, "R = %d exceeds 65535", sp->R);
   if (sp->rand == QMC_RANDOM_SHIFT) {
     if (!sp->shift) return fail(QMC_EINVAL, "shift is null");
@@ -351,8 +357,23 @@ qmc_status qmc_points_init(qmc_points *out, const qmc_point_spec *sp) {
       if (sp->dshift[i] >> 52) return fail(QMC_EINVAL, "dshift[%lld] >= 2^52", (long long)i);
   }
   if (sp->map < QMC_MAP_ID || sp->map > QMC_MAP_TENT) return fail(QMC_EINVAL, "unknown map %d", sp->map);
-  if (sp->map == QMC_MAP_INVNORM && sp->rand == QMC_NO_SHIFT)
+  if (sp->map == QMC_MAP_INVNORM && sp->rand == QMC_NO_SHIFT && !iid)
     return fail(QMC_EINVAL, "the inverse-normal map needs a shift (x_0 = 0)");
+  std::vector<int64_t> soff(s);
+  int64_t sample_total = 0;
+  for (int j = 0; j < s; ++j) {
+    soff[j] = sample_total;
+    sample_total += int64_t(1) << nbv[j];
+  }
+  if (iid) {
+    if (!sp->samples) return fail(QMC_EINVAL, "samples is null");
+    const bool open = sp->map == QMC_MAP_INVNORM;
+    for (int64_t i = 0; i < (int64_t)sp->R * sample_total; ++i) {
+      const double u = sp->samples[i];
+      if (!(u >= 0.0 && u < 1.0) || (open && u == 0.0))
+        return fail(QMC_EINVAL, "samples[%lld] = %g outside %s", (long long)i, u, open ? "(0,1)" : "[0,1)");
+    }
+  }
 
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(QMC_EDEVICE, "no HIP device");
@@ -390,6 +411,18 @@ qmc_status qmc_points_init(qmc_points *out, const qmc_point_spec *sp) {
     if ((e = hipMemcpy(p->d_dshift, sp->dshift, nshift * 8, hipMemcpyHostToDevice)) != hipSuccess)
       return cleanup(hip_fail(e, "hipMemcpy"));
   }
+  if (iid) {
+    const size_t nsamp = (size_t)sp->R * sample_total;
+    if ((e = hipMalloc(&p->d_samples, nsamp * 8)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc"));
+    if ((e = hipMemcpy(p->d_samples, sp->samples, nsamp * 8, hipMemcpyHostToDevice)) != hipSuccess)
+      return cleanup(hip_fail(e, "hipMemcpy"));
+    if ((e = hipMalloc(&p->d_soff, (size_t)s * 8)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc"));
+    if ((e = hipMemcpy(p->d_soff, soff.data(), (size_t)s * 8, hipMemcpyHostToDevice)) != hipSuccess)
+      return cleanup(hip_fail(e, "hipMemcpy"));
+  }
+  p->D.samples = static_cast<const double *>(p->d_samples);
+  p->D.soff = static_cast<const int64_t *>(p->d_soff);
+  p->D.sample_total = sample_total;
   p->D.gen = static_cast<const uint32_t *>(p->d_gen);
   p->D.nbj = static_cast<const int32_t *>(p->d_nb);
   p->D.shift = static_cast<const double *>(p->d_shift);
@@ -405,6 +438,8 @@ qmc_status qmc_points_free(qmc_points p) {
   if (p->d_nb) (void)hipFree(p->d_nb);
   if (p->d_shift) (void)hipFree(p->d_shift);
   if (p->d_dshift) (void)hipFree(p->d_dshift);
+  if (p->d_samples) (void)hipFree(p->d_samples);
+  if (p->d_soff) (void)hipFree(p->d_soff);
   delete p;
   return QMC_OK;
 }

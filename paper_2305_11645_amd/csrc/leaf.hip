@@ -721,7 +721,8 @@ hipError_t launch_leaf(const Geometry &G, int mode, const qmc_integrand &f, cons
   a.gy = lp.gy;
   a.nparts = lp.gx * lp.gy;
   // largest |x| of a point value after the map (bounds the cos argument)
-  a.xmax = G.map == QMC_MAP_INVNORM ? 8.5f : 1.0f;
+  // (Phi^-1 of any positive double is below 38.5 in magnitude)
+  a.xmax = G.map == QMC_MAP_INVNORM ? 40.0f : 1.0f;
   const dim3 grid(lp.gx, lp.gy, nr), block(64 * lp.nw);
   const size_t lds = leaf_lds_bytes(G, mode, lp.cpl, lp.nw);
   const void *fn = leaf_fn(G, mode, f.g, lp.cpl);

@@ -66,6 +66,9 @@ struct DevSpec {
   const int32_t *nbj;      // [s] m - min(w_j, m)
   const double *shift;     // [R*s]
   const uint64_t *dshift;  // [R*s]
+  const double *samples;   // reduced Monte Carlo: [R][sample_total]
+  const int64_t *soff;     // [s] start of coordinate j's samples in a replicate
+  int64_t sample_total;    // sum_j n_j
 };
 
 // Per-call timing hook (no-op unless enabled).

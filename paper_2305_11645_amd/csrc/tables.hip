@@ -96,12 +96,17 @@ __device__ __forceinline__ double ppnd16(double p) {
 template <bool INVNORM>
 __device__ __forceinline__ double value_f64(const PointConsts &G, const DevSpec &D, int r, int j,
                                             uint32_t rho, int nb) {
-  const uint32_t c = value_int(G, D.gen, j, rho, nb);
   double x;
-  if (G.rand == QMC_DIGITAL_SHIFT) {
+  if (G.kind == QMC_IID) {
+    // reduced Monte Carlo (Section 4, eq. randpts): the distinct values of
+    // coordinate j are its own i.i.d. samples, point k taking sample k mod n_j
+    x = D.samples[(size_t)r * D.sample_total + D.soff[j] + rho];
+  } else if (G.rand == QMC_DIGITAL_SHIFT) {
+    const uint32_t c = value_int(G, D.gen, j, rho, nb);
     const uint64_t U = ((uint64_t)c << (52 - nb)) ^ D.dshift[(size_t)r * G.s + j];
     x = (double)(2 * U + 1) * 0x1p-53;  // exact
   } else {
+    const uint32_t c = value_int(G, D.gen, j, rho, nb);
     x = (double)c * __builtin_ldexp(1.0, -nb);  // exact
     if (G.rand == QMC_RANDOM_SHIFT) {
       x = __dadd_rn(x, D.shift[(size_t)r * G.s + j]);

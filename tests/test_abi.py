@@ -45,6 +45,7 @@ def _spec(wl, **over):
     gen = np.ascontiguousarray(over.pop("gen", wl.gen), dtype=np.uint64)
     shift = over.pop("shift", wl.shift)
     dshift = over.pop("dshift", wl.dshift)
+    samples = over.pop("samples", wl.samples)
     arrs["w"], arrs["gen"] = w, gen
     sp = _lib.PointSpec(b=over.pop("b", 2), m=over.pop("m", wl.m), s=over.pop("s", wl.s),
                         kind=over.pop("kind", wl.kind),
@@ -57,6 +58,9 @@ def _spec(wl, **over):
     if dshift is not None:
         arrs["dshift"] = np.ascontiguousarray(dshift, dtype=np.uint64)
         sp.dshift = arrs["dshift"].ctypes.data_as(ct.POINTER(ct.c_uint64))
+    if samples is not None:
+        arrs["samples"] = np.ascontiguousarray(samples, dtype=np.float64)
+        sp.samples = arrs["samples"].ctypes.data_as(ct.POINTER(ct.c_double))
     assert not over, over
     return sp, arrs
 
@@ -98,6 +102,49 @@ def test_points_init_validation(name, make, code):
     st, msg = _init_status(sp)
     assert st == code, (name, st, msg)
     assert msg
+
+
+def iid(**kw):
+    return I.make_custom(kind=I.IID, m=7, s=9, t=4, w=I.w_log2(9, 8), R=3, **kw)
+
+
+def _bad_sample(wl, value):
+    x = wl.samples.copy()
+    x[2, 5] = value
+    return x
+
+
+IID_CASES = [
+    ("with a random shift", lambda wl: _spec(wl, rand=I.RANDOM_SHIFT, shift=np.full((3, 9), 0.5)), 1),
+    ("samples missing", lambda wl: _spec(wl, samples=None), 1),
+    ("sample equal to one", lambda wl: _spec(wl, samples=_bad_sample(wl, 1.0)), 1),
+    ("negative sample", lambda wl: _spec(wl, samples=_bad_sample(wl, -0.25)), 1),
+    ("NaN sample", lambda wl: _spec(wl, samples=_bad_sample(wl, float("nan"))), 1),
+    ("zero sample under Phi^-1", lambda wl: _spec(wl, map=I.MAP_INVNORM, samples=_bad_sample(wl, 0.0)), 1),
+]
+
+
+@pytest.mark.parametrize("name,make,code", IID_CASES, ids=[c[0] for c in IID_CASES])
+def test_iid_points_init_validation(name, make, code):
+    """Reduced Monte Carlo (Section 4): no shift, R independent replicates, and
+    caller samples in [0,1) ((0,1) under the inverse-normal map)."""
+    sp, keep = make(iid())
+    st, msg = _init_status(sp)
+    assert st == code, (name, st, msg)
+    assert msg
+
+
+def test_iid_valid_spec_reaches_the_device_check():
+    """A valid reduced Monte Carlo spec with R > 1, no shift, Phi^-1 and a zero
+    sample allowed only without that map passes validation (no GPU here)."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible: the no-device path is not reachable")
+    for mp in (I.MAP_ID, I.MAP_INVNORM):
+        wl = iid(map=mp)
+        sp, keep = _spec(wl, samples=_bad_sample(wl, 0.0) if mp == I.MAP_ID else wl.samples)
+        st, msg = _init_status(sp)
+        assert st == 4 and "device" in msg, msg
 
 
 def test_digital_shift_range():

@@ -249,6 +249,70 @@ def test_autograd_matches_grad():
     assert torch.allclose(A.grad, ref, rtol=1e-6, atol=1e-12)
 
 
+# ------------------------------------------------------------------ reduced Monte Carlo (Section 4)
+
+def iid_small(mp=I.MAP_ID, m=9, s=40, t=100, R=3, seed=4, w=None, g=I.G_COS, h=I.H_ID, K=0.0, c=1.0,
+              A_scale=0.3):
+    if w is None:
+        w = I.w_log2(s, m + 1)
+    return I.make_custom(kind=I.IID, m=m, s=s, t=t, w=w, rand=I.NO_SHIFT, R=R, map=mp, g=g, h=h, K=K,
+                         c=c, seed=seed, A_scale=A_scale)
+
+
+@pytest.mark.parametrize("mp", [I.MAP_ID, I.MAP_CENTER, I.MAP_TENT, I.MAP_INVNORM])
+def test_iid_tables_bit_exact(mp):
+    """eq. randpts: the device tables are the caller's samples after the map,
+    bit for bit (the inverse-normal map to 1e-14)."""
+    torch = torch_cuda()
+    wl = iid_small(mp, m=10, s=24)
+    pts = q.Points.from_workload(wl)
+    for r in range(wl.R):
+        ref = oracle_tables(wl, r)
+        for j in range(wl.s):
+            got = q.point_values(pts, r, j).cpu().numpy()
+            if mp == I.MAP_INVNORM:
+                np.testing.assert_allclose(got, ref[j], rtol=1e-14, atol=0)
+            else:
+                np.testing.assert_array_equal(got, ref[j])
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("prec", [I.FP32, I.SPLIT_BF16X3])
+def test_iid_matvec_elementwise(prec):
+    """Reduced Monte Carlo products Y = X A, every element within the bound."""
+    torch = torch_cuda()
+    wl = iid_small(I.MAP_INVNORM, A_scale=0.1)
+    pts = q.Points.from_workload(wl)
+    A = to_dev(wl.A, torch)
+    for r in range(wl.R):
+        Y = q.reduced_matvec(pts, A, r=r, prec=prec).cpu().numpy()
+        rel = _check_Y(wl, Y, r, prec)
+        assert rel < (1e-6 if prec == I.FP32 else 2e-4)
+
+
+@pytest.mark.parametrize("g,h,c,mp", [(I.G_COS, I.H_ID, 1.0, I.MAP_ID), (I.G_EXP, I.H_ID, -0.7, I.MAP_CENTER),
+                                      (I.G_EXP, I.H_CALL, 0.2, I.MAP_INVNORM)])
+def test_iid_estimate_and_gradient(g, h, c, mp):
+    """Estimates of every replicate within 1e-6 and their gradients within 1e-6
+    (Frobenius) of the oracle."""
+    from oracle import oracle as O
+    torch = torch_cuda()
+    K = 1.0 if h == I.H_CALL else 0.0
+    wl = iid_small(mp, m=10, s=50, t=80, g=g, h=h, c=c, K=K)
+    pts = q.Points.from_workload(wl)
+    A = to_dev(wl.A, torch)
+    f = q.Integrand_.of(wl)
+    Q = q.estimate(pts, A, f).cpu().numpy()
+    Qo, _ = O.estimate(wl)
+    assert np.all(np.abs(Q - Qo) <= Q_TOL * np.maximum(np.abs(Qo), 1e-3)), (Q, Qo)
+    Qg, dA = q.estimate_grad(pts, A, f)
+    _, dAo = O.estimate_grad(wl)
+    dA = dA.cpu().numpy().astype(np.float64)
+    for r in range(wl.R):
+        rel = np.linalg.norm(dA[r] - dAo[r]) / np.linalg.norm(dAo[r])
+        assert rel <= 1e-6, rel
+
+
 # ------------------------------------------------------------------ full-size workloads
 
 def _expected():
@@ -257,7 +321,7 @@ def _expected():
         return json.load(fh)
 
 
-@pytest.mark.parametrize("c", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("c", [1, 2, 3, 4, 5, 6])
 def test_full_config_estimate(c):
     """Each workload at its full size, in the launch configuration the
     benchmark times: Q[r] within 1e-6 relative of the stored oracle values."""
@@ -275,7 +339,7 @@ def test_full_config_estimate(c):
         assert rel.max() <= Q_TOL, (c, prec, rel)
 
 
-@pytest.mark.parametrize("c", [2, 3, 4, 5])
+@pytest.mark.parametrize("c", [2, 3, 4, 5, 6])
 def test_full_config_sampled_rows(c):
     """qmc_reduced_matvec at full size: 48 sampled rows of Y = X A against the
     oracle's FP64 rows (tables indexed by k mod n_j), element-wise bound."""
