@@ -59,6 +59,9 @@ def lib():
         L.qo_estimate.argtypes = [P, DP, ct.c_int, ct.POINTER(_Integrand), DP, I64P]
         L.qo_estimate_grad.argtypes = [P, DP, ct.c_int, ct.POINTER(_Integrand), DP, DP]
         L.qo_reduced_matvec.argtypes = [P, ct.c_int, DP, ct.c_int, DP, I64P]
+        L.qo_alg4.argtypes = [P, ct.c_int, DP, ct.c_int, ct.c_int, ct.c_int, DP, I64P]
+        L.qo_output_values.argtypes = [P, ct.c_int, ct.c_int, DP]
+        L.qo_net_is_periodic.argtypes = [P]
         L.qo_invnorm.argtypes = [ct.c_double]
         L.qo_invnorm.restype = ct.c_double
         L.qo_neumaier.argtypes = [DP, ct.c_int64]
@@ -136,6 +139,32 @@ def alg1(wl, r: int, A: np.ndarray | None = None, i0: int = 0, i1: int | None = 
     rc = lib().qo_alg1(ct.byref(sp.c), r, _dp(A), t, i0, i1, _dp(P), ct.byref(cnt))
     assert rc == 0
     return P, int(cnt.value)
+
+
+def alg4(wl, r: int, A: np.ndarray | None = None, i0: int = 0, i1: int | None = None):
+    """Algorithm 4 on columns [i0, i1) for shift r: (P, multiplication count)."""
+    sp = Spec(wl)
+    A = _A64(wl) if A is None else np.ascontiguousarray(A, dtype=np.float64)
+    t = A.shape[1]
+    i1 = t if i1 is None else i1
+    P = np.empty((wl.N, i1 - i0), dtype=np.float64)
+    cnt = ct.c_int64(0)
+    rc = lib().qo_alg4(ct.byref(sp.c), r, _dp(A), t, i0, i1, _dp(P), ct.byref(cnt))
+    assert rc == 0
+    return P, int(cnt.value)
+
+
+def output_values(wl, r: int, j: int) -> np.ndarray:
+    """Values of coordinate j indexed by the integer of its reduced output digits."""
+    sp = Spec(wl)
+    n = 1 << int(wl.nbits()[j])
+    out = np.empty(n, dtype=np.float64)
+    assert lib().qo_output_values(ct.byref(sp.c), r, j, _dp(out)) == 0
+    return out
+
+
+def net_is_periodic(wl) -> bool:
+    return bool(lib().qo_net_is_periodic(ct.byref(Spec(wl).c)))
 
 
 def reduced_matvec(wl, r: int = 0, A: np.ndarray | None = None) -> np.ndarray:

@@ -341,6 +341,80 @@ int qo_alg1(const qo_spec *sp, int r, const double *A, int t, int i0, int i1,
     return 0;
 }
 
+/* ------------------------------------------------------------ Algorithm 4 */
+
+/*
+ * A reduced net is periodic in k with period n_j (and Algorithm 1 applies)
+ * when its reduced matrix has zero columns q > n_j; otherwise coordinate j
+ * depends on every digit of k and the product needs Algorithm 4.
+ */
+static int net_is_periodic(const qo_spec *sp) {
+    if (sp->kind != QO_DIGITAL_NET) return 1;
+    for (int j = 0; j < sp->s; ++j) {
+        int nb = nbits_of(sp, j);
+        uint64_t mask = nb >= 64 ? ~UINT64_C(0) : ((UINT64_C(1) << nb) - 1);
+        for (int q = nb; q < sp->m; ++q)
+            if (sp->gen[(size_t)j * sp->m + q] & mask) return 0;
+    }
+    return 1;
+}
+
+int qo_net_is_periodic(const qo_spec *sp) { return net_is_periodic(sp); }
+
+/* Values X_j[c] of coordinate j indexed by the integer c of the reduced output
+ * digits (x = c / 2^nb before shift and map), c < n_j: the n_j possible values
+ * of Section 3 (after eq. reduced_genmat_net2). */
+int qo_output_values(const qo_spec *sp, int r, int j, double *out) {
+    int nb = nbits_of(sp, j);
+    uint64_t n = UINT64_C(1) << nb;
+    for (uint64_t c = 0; c < n; ++c) out[c] = shift_and_map(sp, r, j, c, nb);
+    return 0;
+}
+
+/*
+ * Algorithm 4 (fast reduced matrix product for digital nets) on the column
+ * block [i0, i1) for shift r: for j = s*..1, the row vectors
+ * c_k = X_j[k] a_j (k < n_j) are formed and P_j = P_{j+1} + (c_{k_j(n)})_n,
+ * k_j(n) = floor(y_{n,j} n_j) = the integer of the reduced output digits of n.
+ * The multiplication count (n_j per column) is added to *nmadd.
+ */
+int qo_alg4(const qo_spec *sp, int r, const double *A, int t, int i0, int i1,
+            double *P, int64_t *nmadd) {
+    int tb = i1 - i0;
+    int64_t N = (int64_t)1 << sp->m;
+    for (int64_t e = 0; e < N * tb; ++e) P[e] = 0.0;
+    double *v = (double *)malloc(sizeof(double) * ((size_t)1 << sp->m));
+    double *c = (double *)malloc(sizeof(double) * ((size_t)1 << sp->m) * tb);
+    if (!v || !c) { free(v); free(c); return 1; }
+    int64_t count = 0;
+    for (int j = sp->s - 1; j >= 0; --j) {
+        if (column_is_zero(sp, j)) continue;
+        int nb = nbits_of(sp, j);
+        int64_t nj = (int64_t)1 << nb;
+        qo_output_values(sp, r, j, v);
+        const double *aj = A + (size_t)j * t + i0;
+        for (int64_t k = 0; k < nj; ++k)
+            for (int i = 0; i < tb; ++i) c[k * tb + i] = v[k] * aj[i];
+        if (sp->w[j] < sp->m) count += nj * tb;
+#pragma omp parallel for schedule(static)
+        for (int64_t n = 0; n < N; ++n) {
+            uint64_t k = unreduced_int_over_N(sp, j, (uint64_t)n) >> (sp->m - nb);
+            for (int i = 0; i < tb; ++i) P[n * tb + i] = P[n * tb + i] + c[k * tb + i];
+        }
+    }
+    free(v); free(c);
+    if (nmadd) *nmadd += count;
+    return 0;
+}
+
+/* The reduced product of one column block: Algorithm 1 when the point set is
+ * periodic after reduction, Algorithm 4 otherwise. */
+static int reduced_product(const qo_spec *sp, int r, const double *A, int t, int i0, int i1,
+                           double *P, int64_t *nmadd) {
+    return net_is_periodic(sp) ? qo_alg1(sp, r, A, t, i0, i1, P, nmadd)
+                               : qo_alg4(sp, r, A, t, i0, i1, P, nmadd);
+}
+
 /* ------------------------------------------------------------ integrand */
 
 static double g_val(const qo_integrand *f, double y) {
@@ -391,7 +465,7 @@ static int point_means(const qo_spec *sp, int r, const double *A, int t,
     int tb = block_width(t);
     for (int i0 = 0; i0 < t; i0 += tb) {
         int i1 = i0 + tb < t ? i0 + tb : t, w = i1 - i0;
-        if (qo_alg1(sp, r, A, t, i0, i1, P, nmadd)) return 1;
+        if (reduced_product(sp, r, A, t, i0, i1, P, nmadd)) return 1;
 #pragma omp parallel for schedule(static)
         for (int64_t k = 0; k < N; ++k)
             for (int i = 0; i < w; ++i) u[k] = u[k] + g_val(f, P[k * w + i]);
@@ -428,6 +502,7 @@ int qo_estimate(const qo_spec *sp, const double *A, int t, const qo_integrand *f
  */
 int qo_estimate_grad(const qo_spec *sp, const double *A, int t, const qo_integrand *f,
                      double *Q, double *dA) {
+    if (!net_is_periodic(sp)) return 2;  /* the fold below needs periodic tables */
     int64_t N = (int64_t)1 << sp->m;
     int s = sp->s, tb = block_width(t);
     double *P = (double *)malloc(sizeof(double) * (size_t)N * tb);
@@ -485,7 +560,7 @@ int qo_reduced_matvec(const qo_spec *sp, int r, const double *A, int t, double *
     if (!P) return 1;
     for (int i0 = 0; i0 < t; i0 += tb) {
         int i1 = i0 + tb < t ? i0 + tb : t, w = i1 - i0;
-        qo_alg1(sp, r, A, t, i0, i1, P, nmadd);
+        if (reduced_product(sp, r, A, t, i0, i1, P, nmadd)) { free(P); return 1; }
         for (int64_t k = 0; k < N; ++k) memcpy(Y + k * t + i0, P + k * w, sizeof(double) * w);
     }
     free(P);

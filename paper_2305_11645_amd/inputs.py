@@ -145,6 +145,24 @@ def tridiag_cholesky_T(s: int, diag: float = 0.4, off: float = 0.2) -> np.ndarra
     return np.ascontiguousarray(np.linalg.cholesky(Sig).T)
 
 
+def draw_net_upper(rng: np.random.Generator, s: int, m: int) -> np.ndarray:
+    """Random upper-triangular generating matrices over F_2 with unit diagonal
+    (the shape of Sobol' matrices): C_{p,q} = 0 for p > q, one on the diagonal,
+    fair bits above it.  Column words as in draw_net_lower.  After the row
+    reduction the points still depend on every digit of k (not periodic), so
+    products over them need Algorithm 4."""
+    words = np.zeros(s * m, dtype=np.uint64)
+    for j in range(s):
+        bits = rng.integers(0, 2, size=(m, m))
+        for q in range(m):
+            word = 1 << q
+            for p in range(q):
+                if bits[p, q]:
+                    word |= 1 << p
+            words[j * m + q] = np.uint64(word)
+    return words
+
+
 # ---------------------------------------------------------------- A matrices
 
 def exp_kernel_cholesky_T(n: int, ell: float = 0.1) -> np.ndarray:
@@ -171,6 +189,7 @@ CONFIG_NAMES = {
     4: "C4 KL coefficients reduced lattice m=18 s=2048 t=4096 R=32 exp-mean",
     5: "C5 shifted reduced lattice m=20 s=t=1024 cos-mean gradient",
     6: "C6 reduced Monte Carlo basket call m=20 s=t=512 R=4",
+    7: "C7 digitally shifted reduced Sobol'-type net (Algorithm 4) m=16 s=t=512 R=2 Gaussian cos-mean",
 }
 
 # Basket option of Section 5 (Black-Scholes, zero rate): S_j(0) = 100, T = 1,
@@ -183,7 +202,7 @@ BASKET_K = 110.0 / BASKET_SCALE
 
 def make_config(c: int, seed: int | None = None, *, m: int | None = None, s: int | None = None,
                 t: int | None = None, R: int | None = None, kind: int | None = None) -> Workload:
-    """Build workload C<c> (1..6).  Size overrides give the same recipe at other shapes."""
+    """Build workload C<c> (1..7).  Size overrides give the same recipe at other shapes."""
     if seed is None:
         seed = 1000 + c
     rng = np.random.default_rng(seed)
@@ -245,6 +264,15 @@ def make_config(c: int, seed: int | None = None, *, m: int | None = None, s: int
             raise ValueError("C6 uses a square Cholesky factor: s must equal t")
         A_fn = lambda: tridiag_cholesky_T(s_)
         prec = FP32
+    elif c == 7:
+        m_, s_, t_, R_ = 16, 512, 512, 2
+        m_, s_, t_, R_ = m or m_, s or s_, t or t_, R or R_
+        w = w_log2(s_, max(m_ - 4, 0))
+        kind_ = DIGITAL_NET if kind is None else kind
+        rand, mp = DIGITAL_SHIFT, MAP_INVNORM
+        g, cc, h, K = G_COS, 1.0, H_ID, 0.0
+        A_fn = lambda: rng.standard_normal((s_, t_)) / math.sqrt(s_)
+        prec = FP32
     else:
         raise ValueError(f"unknown workload C{c}")
 
@@ -254,7 +282,7 @@ def make_config(c: int, seed: int | None = None, *, m: int | None = None, s: int
     elif kind_ == POLY_LATTICE:
         gen = draw_poly(rng, nb)
     elif kind_ == DIGITAL_NET:
-        gen = draw_net_lower(rng, s_, m_)
+        gen = draw_net_upper(rng, s_, m_) if c == 7 else draw_net_lower(rng, s_, m_)
     elif kind_ == IID:
         gen = np.ones(s_, dtype=np.uint64)  # unused
     else:
@@ -276,7 +304,7 @@ def make_config(c: int, seed: int | None = None, *, m: int | None = None, s: int
 
 def make_custom(*, kind: int, m: int, s: int, t: int, w: np.ndarray, rand: int = NO_SHIFT,
                 R: int = 1, map: int = MAP_ID, g: int = G_COS, c: float = 1.0, h: int = H_ID,
-                K: float = 0.0, A_scale: float = 1.0, seed: int = 7) -> Workload:
+                K: float = 0.0, A_scale: float = 1.0, seed: int = 7, net: str = "lower") -> Workload:
     """A small random workload of any shape (tests): N(0,1)*A_scale matrix, random generators."""
     rng = np.random.default_rng(seed)
     w = np.asarray(w, dtype=np.int32)
@@ -287,6 +315,8 @@ def make_custom(*, kind: int, m: int, s: int, t: int, w: np.ndarray, rand: int =
         gen = draw_poly(rng, nb)
     elif kind == IID:
         gen = np.ones(s, dtype=np.uint64)  # unused
+    elif net == "upper":
+        gen = draw_net_upper(rng, s, m)
     else:
         gen = draw_net_lower(rng, s, m)
     A64 = rng.standard_normal((s, t)) * A_scale

@@ -482,3 +482,71 @@ def test_reduced_mc_gaussian_mean(oracle_lib):
     exact = float(np.mean(np.exp(wl.c ** 2 * np.sum(A * A, axis=0) / 2)))
     se = np.std(Q, ddof=1) / math.sqrt(wl.R)
     assert abs(np.mean(Q) - exact) <= 4 * se
+
+
+# ------------------------------------------------------------------ Algorithm 4 (general reduced nets)
+
+def upper_net(m=7, s=12, t=5, R=2, rand=I.DIGITAL_SHIFT, mp=I.MAP_CENTER, seed=8, g=I.G_COS, h=I.H_ID, K=0.0):
+    return I.make_custom(kind=I.DIGITAL_NET, m=m, s=s, t=t, w=I.w_log2(s, m + 1), rand=rand, R=R, map=mp,
+                         g=g, h=h, K=K, seed=seed, net="upper")
+
+
+def test_net_periodicity_detection(oracle_lib):
+    """Section 3: after the row reduction a lower-triangular C^{(j)} has zero
+    columns beyond n_j (the points repeat with period n_j); an upper-triangular
+    (Sobol'-type) one does not."""
+    O = oracle_lib
+    assert O.net_is_periodic(small(I.DIGITAL_NET, I.DIGITAL_SHIFT))
+    assert not O.net_is_periodic(upper_net())
+
+
+@pytest.mark.parametrize("rand", RANDS)
+@pytest.mark.parametrize("mp", [I.MAP_ID, I.MAP_CENTER, I.MAP_TENT])
+def test_alg4_output_values_match_points(oracle_lib, rand, mp):
+    """Section 3: coordinate j of the reduced net takes only the n_j values
+    c / n_j (then shifted and mapped); the value of point n is the one with
+    c = floor(y_{n,j} n_j), the integer of its reduced output digits (computed
+    here from brute force's explicit digit vectors)."""
+    O = oracle_lib
+    wl = upper_net(rand=rand, mp=mp, R=2 if rand != I.NO_SHIFT else 1)
+    for r in range(wl.R):
+        X = brute.point_matrix(wl, r)
+        for j in range(wl.s):
+            vals = O.output_values(wl, r, j)
+            nb = wl.m - min(int(wl.w[j]), wl.m)
+            C = brute.reduced_net_matrix(wl, j)
+            for n in range(wl.N):
+                d = brute.digits(n, wl.m)
+                y = [sum(C[p][q] * d[q] for q in range(wl.m)) % 2 for p in range(wl.m)]
+                c = sum(y[p] << (nb - 1 - p) for p in range(nb))
+                assert vals[c] == X[n, j], (r, j, n)
+
+
+@pytest.mark.parametrize("net", ["upper", "lower"])
+def test_alg4_matches_dense(oracle_lib, net):
+    """Algorithm 4 equals the dense product X A of the unreduced net (any
+    generating matrices), with t sum_{j <= s*} n_j multiplications."""
+    O = oracle_lib
+    wl = I.make_custom(kind=I.DIGITAL_NET, m=8, s=20, t=7, w=I.w_log2(20, 9), rand=I.DIGITAL_SHIFT, R=2,
+                       map=I.MAP_INVNORM, seed=12, net=net)
+    A = wl.A.astype(np.float64)
+    nmul = wl.t * sum(2 ** int(n) for n, w in zip(wl.nbits(), wl.w) if w < wl.m)
+    for r in range(wl.R):
+        P, cnt = O.alg4(wl, r)
+        Yd = O.point_matrix_unreduced(wl, r) @ A
+        assert np.linalg.norm(P - Yd) <= 1e-13 * np.linalg.norm(Yd)
+        assert cnt == nmul
+
+
+def test_alg4_estimate_matches_definition(oracle_lib):
+    """For a non-periodic net the oracle's estimate (Algorithm 4) equals
+    eq. QMC-rule evaluated on the dense point matrix."""
+    O = oracle_lib
+    wl = upper_net(m=8, s=16, t=6, R=2, mp=I.MAP_INVNORM, g=I.G_EXP, h=I.H_CALL, K=1.0)
+    wl.c = 0.3
+    Q, _ = O.estimate(wl)
+    for r in range(wl.R):
+        Y = O.point_matrix_unreduced(wl, r) @ wl.A.astype(np.float64)
+        u = np.mean(np.exp(wl.c * Y), axis=1)
+        ref = float(np.mean(np.maximum(u - wl.K, 0.0)))
+        assert abs(Q[r] - ref) <= 1e-13 * max(abs(ref), 1e-300)
