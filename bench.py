@@ -34,6 +34,7 @@ VALU_SLOTS_PER_S = 256 * 128 * 2.4e9
 VALU_PEAK_TFLOPS = 2 * VALU_SLOTS_PER_S / 1e12
 G_SLOTS = {0: 0, 1: 4, 2: 4}  # per evaluation of g: id; cos; exp (one transcendental)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+MFMA_PEAK_TFLOPS = {0: 157.3, 1: 2500.0}  # dense FP32 and BF16 matrix-core peaks
 
 
 def leaf_traffic(config: int, op: str = "estimate"):
@@ -273,12 +274,24 @@ def main() -> int:
     flops = 2.0 * wl.N * wl.s * wl.t * wl.R
     value = flops / (ms * 1e-3) / 1e9
     leaf_ms = kern.get("leaf", {}).get("avg_ms", float("nan"))
-    slots = leaf_algorithmic_slots(wl, pts.split_level)
-    achieved = 2 * slots / (leaf_ms * 1e-3) / 1e12
-    roofline = {"bound": "alu", "kernel": "leaf_kernel", "achieved": round(achieved, 3),
-                "peak": round(VALU_PEAK_TFLOPS, 1), "unit": "TFLOP/s",
-                "frac": round(achieved / VALU_PEAK_TFLOPS, 4), "traffic": leaf_traffic(args.config),
-                "avg_ms": round(leaf_ms, 5), "algorithmic_lane_ops": slots}
+    if pts.split_level < 0:
+        # Algorithm 4 (a net that is not periodic): the tile products run on the
+        # matrix cores, 2 N s t R flops per launch (three BF16 products each
+        # with the split precision)
+        mf = flops * (3 if prec == I.SPLIT_BF16X3 else 1)
+        peak = MFMA_PEAK_TFLOPS[prec]
+        achieved = mf / (leaf_ms * 1e-3) / 1e12
+        roofline = {"bound": "mfma", "kernel": "alg4_kernel", "achieved": round(achieved, 3),
+                    "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+                    "traffic": leaf_traffic(args.config), "avg_ms": round(leaf_ms, 5),
+                    "algorithmic_flops": mf}
+    else:
+        slots = leaf_algorithmic_slots(wl, pts.split_level)
+        achieved = 2 * slots / (leaf_ms * 1e-3) / 1e12
+        roofline = {"bound": "alu", "kernel": "leaf_kernel", "achieved": round(achieved, 3),
+                    "peak": round(VALU_PEAK_TFLOPS, 1), "unit": "TFLOP/s",
+                    "frac": round(achieved / VALU_PEAK_TFLOPS, 4), "traffic": leaf_traffic(args.config),
+                    "avg_ms": round(leaf_ms, 5), "algorithmic_lane_ops": slots}
 
     # accuracy gate and CPU baseline: the FP64 oracle
     rel_err = None

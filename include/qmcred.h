@@ -102,9 +102,11 @@ typedef enum { QMC_H_ID = 0, QMC_H_CALL = 1 /* max(0, u - K) */ } qmc_h;
  *                 iff C^{(j)}_{p,q} = 1 (row p = output digit with weight 2^-p,
  *                 column q = input digit of weight 2^{q-1}).  The library
  *                 applies the reduction of eq. reduced_genmat_net2 itself.
- *                 The reduced matrix must have zero columns q > m - min(w_j,m)
- *                 (true for lower-triangular C^{(j)}); otherwise the points
- *                 are not periodic in k and QMC_EUNSUPPORTED is returned.
+ *                 When the reduced matrix has zero columns q > m - min(w_j,m)
+ *                 (true for lower-triangular C^{(j)}) the points repeat with
+ *                 period n_j and the cascade of Algorithm 2 applies;
+ *                 otherwise (Sobol'-type, upper-triangular C^{(j)}) every
+ *                 product uses Algorithm 4 (Section 3).
  *          reduced Monte Carlo (QMC_IID): ignored (may be NULL).
  *   rand, R, shift [R*s] in [0,1) (QMC_RANDOM_SHIFT) or dshift [R*s] < 2^52
  *                 (QMC_DIGITAL_SHIFT): R independent randomisations, all
@@ -147,8 +149,8 @@ typedef struct qmc_points_s *qmc_points;
  * decreasing, a generator outside its allowed set, shift outside [0,1) or
  * >= 2^52, R < 1, INVNORM without a shift, QMC_IID with a shift, without
  * samples or with a sample outside [0,1) ((0,1) under INVNORM);
- * EUNSUPPORTED: b != 2, m outside [1, 24], a net not periodic after
- * reduction), plans the levels and uploads generators, shifts and samples.
+ * EUNSUPPORTED: b != 2, m outside [1, 24]), plans the levels and uploads
+ * generators, shifts and samples.
  * Synchronous.  *out owns device memory; release with qmc_points_free.
  */
 qmc_status qmc_points_init(qmc_points *out, const qmc_point_spec *spec);
@@ -157,7 +159,9 @@ qmc_status qmc_points_init(qmc_points *out, const qmc_point_spec *spec);
 qmc_status qmc_points_free(qmc_points p);
 
 /* Host-side facts about a point set: N = 2^m, s, R, the split level used by
- * the fused kernels and the number of distinct values sum_j n_j per shift. */
+ * the fused kernels (-1 for a net that is not periodic after reduction, whose
+ * products use Algorithm 4) and the number of distinct values sum_j n_j per
+ * shift. */
 qmc_status qmc_points_info(qmc_points p, int64_t *N, int32_t *s, int32_t *R, int32_t *split_level,
                            int64_t *distinct_values);
 
@@ -165,7 +169,9 @@ qmc_status qmc_points_info(qmc_points p, int64_t *N, int32_t *s, int32_t *R, int
  * Distinct values X_j[rho], rho < n_j, of coordinate j for randomisation r, in
  * FP64 after shift and map (Section 2.1 X_j; Section 2.3 maps).  out: device,
  * n_j doubles.  Integer-exact up to the shift and map; the same FP64
- * operation sequence as the documented randomisations.
+ * operation sequence as the documented randomisations.  For a net that is not
+ * periodic after reduction, rho is the integer of the reduced output digits
+ * (the value is rho / n_j before shift and map; Algorithm 4's index).
  */
 qmc_status qmc_point_values(qmc_points p, int32_t r, int32_t j, double *out, void *stream);
 
@@ -211,6 +217,7 @@ qmc_status qmc_estimate(qmc_points p, const float *A, int32_t t, int64_t lda, co
  * sensitivities over the residue classes k mod n_j, then the distinct values),
  * with Y recomputed rather than stored.  dA: device, R x s x t FP32, rows of
  * length t (leading dimension t).  workspace as above (op = 2).
+ * QMC_EUNSUPPORTED for a net that is not periodic after reduction.
  */
 qmc_status qmc_estimate_grad(qmc_points p, const float *A, int32_t t, int64_t lda,
                              const qmc_integrand *f, int32_t prec, double *Q, float *dA,

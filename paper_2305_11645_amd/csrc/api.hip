@@ -18,6 +18,7 @@ struct qmc_points_s {
   qmc::DevSpec D{};
   void *d_gen = nullptr, *d_nb = nullptr, *d_shift = nullptr, *d_dshift = nullptr;
   void *d_samples = nullptr, *d_soff = nullptr;
+  void *d_yidx = nullptr;  // Algorithm 4 index words
 };
 
 namespace {
@@ -152,6 +153,19 @@ size_t carve(const qmc::Geometry &G, int op, int t, const qmc_integrand *f, int 
   const LeafPlan lp = leaf_plan(G, t, nr, kModeSum, f->g);
   const LeafPlan lg = leaf_plan(G, t, nr, kModeGrad, f->g);
   wk = Work{};
+  if (G.nonperiodic) {  // Algorithm 4: value tables, partials of the 64 x 64 tiles
+    int64_t total = 0;
+    for (int I = 0; I <= G.m; ++I) total += (int64_t)G.lev[I].tau << G.lev[I].nb;
+    wk.tables = c.take<float>((size_t)nr * total);
+    if (op == kOpMatvec) return c.used;
+    const int64_t atct = alg4_col_tiles(t);
+    wk.partial = c.take<double>((size_t)nr * alg4_point_tiles(G) * atct);
+    if (f->h != QMC_H_ID) {
+      wk.ppart = c.take<float>((size_t)nr * atct * G.N);
+      wk.ppartial = c.take<double>((size_t)nr * point_h_blocks(G));
+    }
+    return c.used;
+  }
   wk.tables = c.take<float>((size_t)nr * G.table_total + kTablePad);
   wk.U = c.take<float>((size_t)nr * G.urows * ldu);
   if (op == kOpMatvec) return c.used;
@@ -311,6 +325,7 @@ qmc_status qmc_points_init(qmc_points *out, const qmc_point_spec *sp) {
   std::vector<uint32_t> gen;
   std::vector<int32_t> nbv(s);
   for (int j = 0; j < s; ++j) nbv[j] = m - (sp->w[j] < m ? sp->w[j] : m);
+  bool nonperiodic = false;
   if (sp->kind == QMC_DIGITAL_NET) {
     gen.resize((size_t)s * m);
     for (int j = 0; j < s; ++j) {
@@ -318,10 +333,9 @@ qmc_status qmc_points_init(qmc_points *out, const qmc_point_spec *sp) {
       for (int q = 0; q < m; ++q) {
         const uint64_t wd = sp->gen[(size_t)j * m + q];
         if (wd >> m) return fail(QMC_EINVAL, "net column word (j=%d, q=%d) has bits beyond row m", j, q + 1);
-        if (q >= nbv[j] && (wd & mask))
-          return fail(QMC_EUNSUPPORTED,
-                      "reduced net is not periodic: column %d of coordinate %d is nonzero in its first %d rows",
-                      q + 1, j, nbv[j]);
+        // a column past n_j with bits in the first n_j rows: the reduced net
+        // depends on every digit of k and its products use Algorithm 4
+        if (q >= nbv[j] && (wd & mask)) nonperiodic = true;
         gen[(size_t)j * m + q] = (uint32_t)wd;
       }
     }
@@ -387,6 +401,7 @@ qmc_status qmc_points_init(qmc_points *out, const qmc_point_spec *sp) {
   G.rand = sp->rand;
   G.map = sp->map;
   G.R = sp->R;
+  G.nonperiodic = nonperiodic ? 1 : 0;
   plan_geometry(G, sp->w);
 
   auto cleanup = [&](qmc_status st) {
@@ -416,9 +431,21 @@ qmc_status qmc_points_init(qmc_points *out, const qmc_point_spec *sp) {
     if ((e = hipMalloc(&p->d_samples, nsamp * 8)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc"));
     if ((e = hipMemcpy(p->d_samples, sp->samples, nsamp * 8, hipMemcpyHostToDevice)) != hipSuccess)
       return cleanup(hip_fail(e, "hipMemcpy"));
-    if ((e = hipMalloc(&p->d_soff, (size_t)s * 8)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc"));
-    if ((e = hipMemcpy(p->d_soff, soff.data(), (size_t)s * 8, hipMemcpyHostToDevice)) != hipSuccess)
-      return cleanup(hip_fail(e, "hipMemcpy"));
+  }
+  // start of each coordinate's n_j values (samples of reduced Monte Carlo,
+  // value tables of Algorithm 4)
+  if ((e = hipMalloc(&p->d_soff, (size_t)s * 8)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc"));
+  if ((e = hipMemcpy(p->d_soff, soff.data(), (size_t)s * 8, hipMemcpyHostToDevice)) != hipSuccess)
+    return cleanup(hip_fail(e, "hipMemcpy"));
+  if (nonperiodic) {  // Algorithm 4: index words from the generating matrices, once
+    const size_t words = (size_t)alg4_index_words(G);
+    if ((e = hipMalloc(&p->d_yidx, words * 4)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc"));
+    uint32_t *ylo = static_cast<uint32_t *>(p->d_yidx), *ytile = ylo + (size_t)64 * s;
+    if ((e = launch_alg4_index(G, static_cast<const uint32_t *>(p->d_gen), ylo, ytile, nullptr)) != hipSuccess ||
+        (e = hipDeviceSynchronize()) != hipSuccess)
+      return cleanup(hip_fail(e, "Algorithm 4 index tables"));
+    p->D.ylo = ylo;
+    p->D.ytile = ytile;
   }
   p->D.samples = static_cast<const double *>(p->d_samples);
   p->D.soff = static_cast<const int64_t *>(p->d_soff);
@@ -440,6 +467,7 @@ qmc_status qmc_points_free(qmc_points p) {
   if (p->d_dshift) (void)hipFree(p->d_dshift);
   if (p->d_samples) (void)hipFree(p->d_samples);
   if (p->d_soff) (void)hipFree(p->d_soff);
+  if (p->d_yidx) (void)hipFree(p->d_yidx);
   delete p;
   return QMC_OK;
 }
@@ -450,8 +478,8 @@ qmc_status qmc_points_info(qmc_points p, int64_t *N, int32_t *s, int32_t *R, int
   if (N) *N = p->G.N;
   if (s) *s = p->G.s;
   if (R) *R = p->G.R;
-  if (split_level) *split_level = p->G.split;
-  if (distinct_values) *distinct_values = p->G.table_total;
+  if (split_level) *split_level = p->G.nonperiodic ? -1 : p->G.split;  // -1: Algorithm 4, no cascade
+  if (distinct_values) *distinct_values = p->G.nonperiodic ? p->D.sample_total : p->G.table_total;
   return QMC_OK;
 }
 
@@ -514,6 +542,14 @@ qmc_status qmc_reduced_matvec(qmc_points p, int32_t r, const float *A, int32_t t
   carve(p->G, kOpMatvec, t, &fid, 1, base, wk);
   const int64_t ldu = round_up(t, kTileT);
   const Geometry &G = p->G;
+  if (G.nonperiodic) {  // Algorithm 4
+    QMC_HIP(launch_output_tables(G, p->D, r, 1, wk.tables, st), "tables launch");
+    Alg4Out o{};
+    o.Y = Y;
+    o.ldy = ldy;
+    QMC_HIP(launch_alg4(G, p->D, kModeStoreY, fid, prec, wk.tables, 1, A, t, lda, o, st), "Algorithm 4 launch");
+    return QMC_OK;
+  }
   QMC_HIP(launch_tables(G, p->D, r, 1, wk.tables, nullptr, 0, st), "tables launch");
   QMC_HIP(launch_levels(G, prec, wk.tables, 1, A, t, lda, wk.U, ldu, 1.0f, st), "levels launch");
   LeafOut o{};
@@ -538,6 +574,8 @@ static qmc_status estimate_impl(qmc_points p, const float *A, int32_t t, int64_t
   const Geometry &G = p->G;
   const int nr = G.R;
   const int op = grad ? kOpGrad : kOpEstimate;
+  if (grad && G.nonperiodic)
+    return fail(QMC_EUNSUPPORTED, "the gradient of a net that is not periodic after reduction (Algorithm 4) is not provided");
   Work wk;
   const size_t need = carve(G, op, t, f, nr, nullptr, wk);
   CallWorkspace own;
@@ -550,6 +588,25 @@ static qmc_status estimate_impl(qmc_points p, const float *A, int32_t t, int64_t
   const LeafPlan lg = leaf_plan(G, t, nr, kModeGrad, f->g);
   const bool sep = f->h == QMC_H_ID;
   const double inv_nt = 1.0 / ((double)G.N * (double)t);
+
+  if (G.nonperiodic) {  // Algorithm 4: value tables, then the fused tile products
+    QMC_HIP(launch_output_tables(G, p->D, 0, nr, wk.tables, st), "tables launch");
+    Alg4Out o{};
+    if (sep) {
+      o.partial = wk.partial;
+      QMC_HIP(launch_alg4(G, p->D, kModeSum, *f, prec, wk.tables, nr, A, t, lda, o, st), "Algorithm 4 launch");
+      QMC_HIP(launch_reduce(wk.partial, nr, alg4_point_tiles(G) * alg4_col_tiles(t), inv_nt, Q, st),
+              "reduce launch");
+    } else {
+      o.ppart = wk.ppart;
+      QMC_HIP(launch_alg4(G, p->D, kModePoint, *f, prec, wk.tables, nr, A, t, lda, o, st), "Algorithm 4 launch");
+      const int64_t blocks = point_h_blocks(G);
+      QMC_HIP(launch_point_h(G, *f, wk.ppart, nr, alg4_col_tiles(t), t, wk.ppartial, blocks, nullptr, 1.0, st),
+              "point h launch");
+      QMC_HIP(launch_reduce(wk.ppartial, nr, blocks, 1.0 / (double)G.N, Q, st), "reduce launch");
+    }
+    return QMC_OK;
+  }
 
   QMC_HIP(launch_tables(G, p->D, 0, nr, wk.tables, nullptr, 0, st), "tables launch");
   const int leaf_mode = !sep ? kModePoint : (grad ? kModeGrad : kModeSum);

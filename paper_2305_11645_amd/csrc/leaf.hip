@@ -40,30 +40,6 @@ constexpr int kRootBatch = 8;  // upper-level rows of a subtree root loaded toge
 constexpr int kStagePerThread = 8;  // elements of A per thread and staging pass
 static_assert(kMaxUpPadded % kRootBatch == 0, "root batches must tile the padded level arrays");
 
-// cos and sin take the angle in revolutions on v_cos / v_sin; v_fract reduces
-// it exactly.  exp(c y) = 2^(y'), y' = c log2(e) y, on v_exp.
-template <int GF>
-__device__ __forceinline__ float g_val(float ys) {
-  if (GF == QMC_G_COS) return __builtin_amdgcn_cosf(__builtin_amdgcn_fractf(ys));
-  if (GF == QMC_G_EXP) return __builtin_amdgcn_exp2f(ys);
-  return ys;
-}
-
-// Same, for an argument known to lie inside v_cos's input domain (+-256 revolutions).
-template <int GF>
-__device__ __forceinline__ float g_val_near(float ys) {
-  if (GF == QMC_G_COS) return __builtin_amdgcn_cosf(ys);
-  return g_val<GF>(ys);
-}
-
-// g'(y) from the scaled argument y'; c is the parameter of exp(c y)
-template <int GF>
-__device__ __forceinline__ float g_der(float ys, float c) {
-  if (GF == QMC_G_COS) return -__builtin_amdgcn_sinf(__builtin_amdgcn_fractf(ys));
-  if (GF == QMC_G_EXP) return c * __builtin_amdgcn_exp2f(ys);
-  return 1.0f;
-}
-
 // Summing mode, lean form.  A lane carries CPL columns of A (the wave 64 CPL
 // columns), so every point value loaded into a scalar register feeds CPL
 // multiply-adds.  Only the per-level counts tau_I travel with the kernel (one

@@ -47,6 +47,7 @@ struct Level {
 // Everything a kernel needs to know about the point set (passed by value).
 struct Geometry {
   int32_t m, s, kind, rand, map, R;
+  int32_t nonperiodic;   // a reduced net that is not periodic: products by Algorithm 4
   int32_t split;         // L'
   int32_t jlow;          // rows 0..jlow-1 of A belong to the lower levels
   int32_t nup;           // number of upper levels with tau > 0
@@ -69,7 +70,36 @@ struct DevSpec {
   const double *samples;   // reduced Monte Carlo: [R][sample_total]
   const int64_t *soff;     // [s] start of coordinate j's samples in a replicate
   int64_t sample_total;    // sum_j n_j
+  // Algorithm 4 index words (nets that are not periodic): ylo[j * 64 + r] =
+  // y_j(r) for r < 64, ytile[h * s + j] = y_j(64 h)
+  const uint32_t *ylo;
+  const uint32_t *ytile;
 };
+
+// The integrand's g on the scaled argument y' = sigma y (sigma folded into the
+// staged rows of A).  // cos and sin take the angle in revolutions on v_cos / v_sin; v_fract reduces
+// it exactly.  exp(c y) = 2^(y'), y' = c log2(e) y, on v_exp.
+template <int GF>
+__device__ __forceinline__ float g_val(float ys) {
+  if (GF == QMC_G_COS) return __builtin_amdgcn_cosf(__builtin_amdgcn_fractf(ys));
+  if (GF == QMC_G_EXP) return __builtin_amdgcn_exp2f(ys);
+  return ys;
+}
+
+// Same, for an argument known to lie inside v_cos's input domain (+-256 revolutions).
+template <int GF>
+__device__ __forceinline__ float g_val_near(float ys) {
+  if (GF == QMC_G_COS) return __builtin_amdgcn_cosf(ys);
+  return g_val<GF>(ys);
+}
+
+// g'(y) from the scaled argument y'; c is the parameter of exp(c y)
+template <int GF>
+__device__ __forceinline__ float g_der(float ys, float c) {
+  if (GF == QMC_G_COS) return -__builtin_amdgcn_sinf(__builtin_amdgcn_fractf(ys));
+  if (GF == QMC_G_EXP) return c * __builtin_amdgcn_exp2f(ys);
+  return 1.0f;
+}
 
 // Per-call timing hook (no-op unless enabled).
 struct LaunchTimer {
@@ -94,6 +124,12 @@ hipError_t launch_tables(const Geometry &G, const DevSpec &D, int r0, int nr, fl
 hipError_t launch_point_values(const Geometry &G, const DevSpec &D, int r, int j, double *out,
                                hipStream_t st);
 // Dense FP32 point matrix for shift r.
+// Algorithm 4 value tables in digit order: T_j[y] = X_j[c] for y < n_j, c the
+// integer of the reduced output digits and y its n_j-digit bit reversal (the
+// digits as the generating matrix produces them); sum_j n_j floats per
+// randomisation, coordinate blocks at DevSpec::soff.
+hipError_t launch_output_tables(const Geometry &G, const DevSpec &D, int r0, int nr, float *out,
+                                hipStream_t st);
 hipError_t launch_point_matrix(const Geometry &G, const DevSpec &D, int r, float *X, int64_t ldx,
                                hipStream_t st);
 
@@ -164,6 +200,26 @@ LeafPlan leaf_plan(const Geometry &G, int t, int nr, int mode, int gf);
 hipError_t launch_leaf(const Geometry &G, int mode, const qmc_integrand &f, const float *tables,
                        const float *U, int nr, int r0, const float *A, int t, int64_t lda,
                        int64_t ldu, const LeafPlan &lp, const LeafOut &o, hipStream_t st);
+
+// Algorithm 4 (nets that are not periodic): one 64-point x 256-column tile per
+// workgroup (alg4_col_tiles(t) column tiles); modes kModeStoreY, kModeSum
+// (partial[r][point tile][column tile]) and kModePoint (ppart[r][column tile][N]).
+// tab: the digit-order value tables of launch_output_tables for the nr
+// randomisations.
+struct Alg4Out {
+  float *Y;
+  int64_t ldy;
+  double *partial;
+  float *ppart;
+};
+int64_t alg4_point_tiles(const Geometry &G);
+int64_t alg4_index_words(const Geometry &G);  // (64 + tiles) * s
+int alg4_col_tiles(int t);
+hipError_t launch_alg4_index(const Geometry &G, const uint32_t *gen, uint32_t *ylo, uint32_t *ytile,
+                             hipStream_t st);
+hipError_t launch_alg4(const Geometry &G, const DevSpec &D, int mode, const qmc_integrand &f,
+                       int prec, const float *tab, int nr, const float *A, int t, int64_t lda,
+                       const Alg4Out &o, hipStream_t st);
 
 // Q[r] = scale * sum of partial[r][*] (fixed order, compensated).
 hipError_t launch_reduce(const double *partial, int nr, int64_t per, double scale, double *Q,

@@ -21,14 +21,25 @@ namespace qmc {
 // The point-set constants the value computation needs.
 struct PointConsts {
   int32_t m, s, kind, rand, map;
+  int32_t by_output;    // rho is already the integer c of the value c / 2^nb (value tables of nets)
+  int32_t nonperiodic;  // a reduced net that depends on every input digit
 };
 
-static PointConsts consts_of(const Geometry &G) { return PointConsts{G.m, G.s, G.kind, G.rand, G.map}; }
+static PointConsts consts_of(const Geometry &G) {
+  return PointConsts{G.m, G.s, G.kind, G.rand, G.map, 0, G.nonperiodic};
+}
 
+// The integer c of the value c / 2^nb of coordinate j at input index rho:
+// lattice rho z' mod 2^nb; polynomial lattice the carry-less product; net the
+// XOR of the generating-matrix columns selected by the digits of rho (all of
+// them: for a net that repeats with period n_j the columns past nb carry no
+// bits in the first nb rows), truncated to nb rows and read most significant
+// digit first.
 __device__ __forceinline__ uint32_t value_int(const PointConsts &G, const uint32_t *__restrict__ gen,
                                               int j, uint32_t rho, int nb) {
   if (nb == 0) return 0u;
   const uint32_t mask = (nb >= 32) ? 0xffffffffu : ((1u << nb) - 1u);
+  if (G.by_output) return rho & mask;
   if (G.kind == QMC_LATTICE) return (rho * gen[j]) & mask;
   if (G.kind == QMC_POLY_LATTICE) {
     const uint32_t g = gen[j];
@@ -39,8 +50,7 @@ __device__ __forceinline__ uint32_t value_int(const PointConsts &G, const uint32
   }
   const uint32_t *col = gen + (size_t)j * G.m;
   uint32_t y = 0;
-  for (int q = 0; q < nb; ++q)
-    if ((rho >> q) & 1u) y ^= col[q];
+  for (uint32_t b = rho; b; b &= b - 1u) y ^= col[__builtin_ctz(b)];
   y &= mask;  // rows p > nb of the reduced matrix are zero
   return __builtin_bitreverse32(y) >> (32 - nb);
 }
@@ -208,7 +218,8 @@ __global__ void point_matrix_kernel(PointConsts G, DevSpec D, int r, float *__re
     const int64_t k = idx / G.s;
     const int j = (int)(idx - k * G.s);
     const int nb = D.nbj[j];
-    const uint32_t rho = (uint32_t)(k & ((int64_t(1) << nb) - 1));
+    // a net that is not periodic needs every digit of k
+    const uint32_t rho = G.nonperiodic ? (uint32_t)k : (uint32_t)(k & ((int64_t(1) << nb) - 1));
     X[k * ldx + j] = (float)value_f64<INVNORM>(G, D, r, j, rho, nb);
   }
 }
@@ -264,10 +275,12 @@ hipError_t launch_point_values(const Geometry &G, const DevSpec &D, int r, int j
   for (int I = 0; I <= G.m; ++I)
     if (j >= G.lev[I].j0 && j < G.lev[I].j0 + G.lev[I].tau) nb = G.lev[I].nb;
   const dim3 grid(grid_for(int64_t(1) << nb, 256));
+  PointConsts pc = consts_of(G);
+  pc.by_output = G.nonperiodic;  // such a net's values are listed by their output digits
   if (G.map == QMC_MAP_INVNORM)
-    hipLaunchKernelGGL(values_kernel<true>, grid, dim3(256), 0, st, consts_of(G), D, r, j, nb, out);
+    hipLaunchKernelGGL(values_kernel<true>, grid, dim3(256), 0, st, pc, D, r, j, nb, out);
   else
-    hipLaunchKernelGGL(values_kernel<false>, grid, dim3(256), 0, st, consts_of(G), D, r, j, nb, out);
+    hipLaunchKernelGGL(values_kernel<false>, grid, dim3(256), 0, st, pc, D, r, j, nb, out);
   return hipGetLastError();
 }
 
@@ -279,6 +292,40 @@ hipError_t launch_point_matrix(const Geometry &G, const DevSpec &D, int r, float
     hipLaunchKernelGGL(point_matrix_kernel<true>, grid, dim3(256), 0, st, consts_of(G), D, r, X, ldx);
   else
     hipLaunchKernelGGL(point_matrix_kernel<false>, grid, dim3(256), 0, st, consts_of(G), D, r, X, ldx);
+  return hipGetLastError();
+}
+
+// Value tables indexed by output digits (Algorithm 4): for every coordinate j
+// and c < n_j, out[(r - r0) * total + soff[j] + c] = X_j[c] in FP32.  The
+// flat index is mapped to its coordinate by a binary search over soff.
+template <bool INVNORM>
+__global__ __launch_bounds__(256) void outvals_kernel(PointConsts G, DevSpec D, int r0,
+                                                      float *__restrict__ out) {
+  const int rl = blockIdx.y;
+  const int64_t total = D.sample_total;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+    int lo = 0, hi = G.s - 1;  // last j with soff[j] <= e
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (D.soff[mid] <= e) lo = mid; else hi = mid - 1;
+    }
+    const int nb = D.nbj[lo];
+    const uint32_t y = (uint32_t)(e - D.soff[lo]);  // digit-order index
+    const uint32_t c = nb == 0 ? 0u : __builtin_bitreverse32(y) >> (32 - nb);
+    out[(int64_t)rl * total + e] = (float)value_f64<INVNORM>(G, D, r0 + rl, lo, c, nb);
+  }
+}
+
+hipError_t launch_output_tables(const Geometry &G, const DevSpec &D, int r0, int nr, float *out,
+                                hipStream_t st) {
+  LaunchTimer tm("tables", st);
+  PointConsts pc = consts_of(G);
+  pc.by_output = 1;
+  const dim3 grid(grid_for(D.sample_total, 256), nr);
+  if (G.map == QMC_MAP_INVNORM)
+    hipLaunchKernelGGL(outvals_kernel<true>, grid, dim3(256), 0, st, pc, D, r0, out);
+  else
+    hipLaunchKernelGGL(outvals_kernel<false>, grid, dim3(256), 0, st, pc, D, r0, out);
   return hipGetLastError();
 }
 

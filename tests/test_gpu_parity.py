@@ -313,6 +313,105 @@ def test_iid_estimate_and_gradient(g, h, c, mp):
         assert rel <= 1e-6, rel
 
 
+# ------------------------------------------------------------------ Algorithm 4 (nets not periodic after reduction)
+
+def upper_small(rand=I.DIGITAL_SHIFT, mp=I.MAP_CENTER, m=9, s=40, t=100, R=2, seed=6, w=None, g=I.G_COS,
+                h=I.H_ID, K=0.0, c=1.0, A_scale=0.3):
+    if w is None:
+        w = I.w_log2(s, m + 1)
+    return I.make_custom(kind=I.DIGITAL_NET, m=m, s=s, t=t, w=w, rand=rand, R=R, map=mp, g=g, h=h, K=K,
+                         c=c, seed=seed, A_scale=A_scale, net="upper")
+
+
+def test_alg4_is_planned_for_upper_triangular_nets():
+    torch_cuda()
+    assert q.Points.from_workload(upper_small()).split_level == -1
+    assert q.Points.from_workload(small(I.DIGITAL_NET, I.DIGITAL_SHIFT)).split_level >= 0
+
+
+@pytest.mark.parametrize("rand", RANDS)
+@pytest.mark.parametrize("mp", [I.MAP_ID, I.MAP_CENTER, I.MAP_TENT, I.MAP_INVNORM])
+def test_alg4_tables_bit_exact(rand, mp):
+    """Section 3: the n_j values c / n_j of each coordinate (indexed by the
+    reduced output digits), shifted and mapped, equal the oracle's bit for bit
+    (the inverse-normal map to 1e-14)."""
+    from oracle import oracle as O
+    if mp == I.MAP_INVNORM and rand == I.NO_SHIFT:
+        pytest.skip("the inverse-normal map requires a shift")
+    torch_cuda()
+    wl = upper_small(rand, mp, m=10, s=24, R=2 if rand != I.NO_SHIFT else 1)
+    pts = q.Points.from_workload(wl)
+    for r in range(wl.R):
+        for j in range(wl.s):
+            got = q.point_values(pts, r, j).cpu().numpy()
+            ref = O.output_values(wl, r, j)
+            if mp == I.MAP_INVNORM:
+                np.testing.assert_allclose(got, ref, rtol=1e-14, atol=0)
+            else:
+                np.testing.assert_array_equal(got, ref)
+
+
+def test_alg4_point_matrix_matches_unreduced():
+    """Every point from all its digits: the FP32 point matrix equals the FP32
+    rounding of the oracle's unreduced net."""
+    from oracle import oracle as O
+    torch_cuda()
+    wl = upper_small(m=9, s=30)
+    pts = q.Points.from_workload(wl)
+    for r in range(wl.R):
+        np.testing.assert_array_equal(q.point_matrix(pts, r).cpu().numpy(),
+                                      O.point_matrix_unreduced(wl, r).astype(np.float32))
+
+
+@pytest.mark.parametrize("rand", RANDS)
+@pytest.mark.parametrize("prec", [I.FP32, I.SPLIT_BF16X3])
+def test_alg4_matvec_elementwise(rand, prec):
+    """Algorithm 4 products Y = X A, every element within the FP32 (split-bf16)
+    bound: several 64-point tiles, two column tiles with a ragged tail, and a
+    coordinate count that is not a multiple of the 32-coordinate step."""
+    torch = torch_cuda()
+    mp = I.MAP_INVNORM if rand == I.DIGITAL_SHIFT else I.MAP_ID
+    wl = upper_small(rand, mp, s=45, R=2 if rand != I.NO_SHIFT else 1)
+    pts = q.Points.from_workload(wl)
+    A = to_dev(wl.A, torch)
+    for r in range(wl.R):
+        Y = q.reduced_matvec(pts, A, r=r, prec=prec).cpu().numpy()
+        rel = _check_Y(wl, Y, r, prec)
+        assert rel < (1e-6 if prec == I.FP32 else 2e-4)
+
+
+@pytest.mark.parametrize("m,s,t", [(4, 7, 3), (6, 33, 64), (11, 70, 130)])
+def test_alg4_matvec_shapes(m, s, t):
+    """Fewer points than one tile (m = 4), exactly one tile (m = 6), many tiles."""
+    torch = torch_cuda()
+    wl = upper_small(I.DIGITAL_SHIFT, I.MAP_CENTER, m=m, s=s, t=t, R=1)
+    pts = q.Points.from_workload(wl)
+    Y = q.reduced_matvec(pts, to_dev(wl.A, torch), r=0).cpu().numpy()
+    _check_Y(wl, Y, 0, I.FP32)
+
+
+@pytest.mark.parametrize("g,h,c,mp", [(I.G_COS, I.H_ID, 1.0, I.MAP_ID), (I.G_EXP, I.H_ID, -0.7, I.MAP_CENTER),
+                                      (I.G_EXP, I.H_CALL, 0.2, I.MAP_INVNORM), (I.G_ID, I.H_ID, 1.0, I.MAP_TENT)])
+def test_alg4_estimate(g, h, c, mp):
+    """Estimates over Algorithm 4 for every integrand family within 1e-6."""
+    from oracle import oracle as O
+    torch = torch_cuda()
+    K = 1.0 if h == I.H_CALL else 0.0
+    wl = upper_small(I.DIGITAL_SHIFT, mp, m=10, s=50, t=80, g=g, h=h, c=c, K=K)
+    pts = q.Points.from_workload(wl)
+    Q = q.estimate(pts, to_dev(wl.A, torch), q.Integrand_.of(wl)).cpu().numpy()
+    Qo, _ = O.estimate(wl)
+    assert np.all(np.abs(Q - Qo) <= Q_TOL * np.maximum(np.abs(Qo), 1e-3)), (Q, Qo)
+
+
+def test_alg4_gradient_is_unsupported():
+    torch = torch_cuda()
+    wl = upper_small()
+    pts = q.Points.from_workload(wl)
+    with pytest.raises(q.QMCUnsupported):
+        q.estimate_grad(pts, to_dev(wl.A, torch), q.Integrand_.of(wl))
+
+
 # ------------------------------------------------------------------ full-size workloads
 
 def _expected():
@@ -321,7 +420,7 @@ def _expected():
         return json.load(fh)
 
 
-@pytest.mark.parametrize("c", [1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("c", [1, 2, 3, 4, 5, 6, 7])
 def test_full_config_estimate(c):
     """Each workload at its full size, in the launch configuration the
     benchmark times: Q[r] within 1e-6 relative of the stored oracle values."""
@@ -355,6 +454,26 @@ def test_full_config_sampled_rows(c):
     del Y
     Yo, mag = oracle_rows(wl, r, ks)
     err = np.abs(Ys - Yo) / (elementwise_bound(wl, I.FP32) * mag + 1e-30)
+    assert err.max() <= 1.0
+
+
+def test_full_config_alg4_sampled_rows():
+    """C7 (Algorithm 4) at full size: 48 sampled rows of Y = X A against the
+    FP64 rows of the oracle's unreduced net, element-wise bound."""
+    from oracle import oracle as O
+    torch = torch_cuda()
+    wl = I.make_config(7)
+    pts = q.Points.from_workload(wl)
+    A = to_dev(wl.A, torch)
+    r = wl.R - 1
+    Y = q.reduced_matvec(pts, A, r=r, prec=I.FP32)
+    rng = np.random.default_rng(7)
+    ks = np.concatenate([[0, 1, wl.N - 1], rng.integers(0, wl.N, 45)])
+    Ys = Y[torch.from_numpy(ks).cuda()].cpu().numpy().astype(np.float64)
+    del Y
+    X = O.point_matrix_unreduced(wl, r)[ks]
+    A64 = wl.A.astype(np.float64)
+    err = np.abs(Ys - X @ A64) / (elementwise_bound(wl, I.FP32) * (np.abs(X) @ np.abs(A64)) + 1e-30)
     assert err.max() <= 1.0
 
 
