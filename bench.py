@@ -37,11 +37,12 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 MFMA_PEAK_TFLOPS = {0: 157.3, 1: 2500.0}  # dense FP32 and BF16 matrix-core peaks
 
 
-def leaf_traffic(config: int, op: str = "estimate"):
-    """HBM bytes per leaf-kernel launch from the committed counter summary of this
-    workload, or None when there is none or the kernel source changed since."""
+def leaf_traffic(config: int, op: str = "estimate", kernel: str = "leaf_kernel"):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary of this workload, or None when there is none or the kernel's sources
+    (listed in the summary) changed since the counters were taken."""
     import hashlib
-    name = f"leaf_kernel_C{config}_counters.md" if op == "estimate" else f"leaf_kernel_{op}_C{config}_counters.md"
+    name = f"{kernel}_C{config}_counters.md" if op == "estimate" else f"{kernel}_{op}_C{config}_counters.md"
     path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
@@ -51,8 +52,8 @@ def leaf_traffic(config: int, op: str = "estimate"):
             k, v = ln.strip().split(":", 1)
             fields[k.strip()] = v.strip()
     csrc = os.path.join(ROOT, "paper_2305_11645_amd", "csrc")
-    sha = hashlib.sha256(open(os.path.join(csrc, "leaf.hip"), "rb").read()
-                         + open(os.path.join(csrc, "qmc_internal.h"), "rb").read()).hexdigest()[:16]
+    sources = fields.get("kernel_sources", "leaf.hip qmc_internal.h").split()
+    sha = hashlib.sha256(b"".join(open(os.path.join(csrc, f), "rb").read() for f in sources)).hexdigest()[:16]
     if fields.get("kernel_source_sha256_16") != sha or "hbm_bytes_per_dispatch" not in fields:
         return None
     return int(fields["hbm_bytes_per_dispatch"])
@@ -283,7 +284,7 @@ def main() -> int:
         achieved = mf / (leaf_ms * 1e-3) / 1e12
         roofline = {"bound": "mfma", "kernel": "alg4_kernel", "achieved": round(achieved, 3),
                     "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-                    "traffic": leaf_traffic(args.config), "avg_ms": round(leaf_ms, 5),
+                    "traffic": leaf_traffic(args.config, kernel="alg4_kernel"), "avg_ms": round(leaf_ms, 5),
                     "algorithmic_flops": mf}
     else:
         slots = leaf_algorithmic_slots(wl, pts.split_level)

@@ -51,8 +51,18 @@ struct Alg4Args {
   float sigma;           // y' = sigma y (scale of g)
 };
 
+// Buffer resource of `bytes` bytes at `base` (raw, stride 0): loads at byte
+// offsets at or past `bytes` return zero.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_rsrc(const void *base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+__device__ __forceinline__ float load_f32(__amdgpu_buffer_rsrc_t r, uint32_t byte_off) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)byte_off, 0, 0));
+}
+
 template <int PREC, int MODE, int GF>
-__global__ __launch_bounds__(256) void alg4_kernel(Alg4Args a, DevSpec D, const float *__restrict__ tab,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC == QMC_FP32 ? 3 : 2))) void alg4_kernel(Alg4Args a, DevSpec D, const float *__restrict__ tab,
                                                    const float *__restrict__ A, float *__restrict__ Y,
                                                    double *__restrict__ partial,
                                                    float *__restrict__ ppart) {
@@ -65,28 +75,28 @@ __global__ __launch_bounds__(256) void alg4_kernel(Alg4Args a, DevSpec D, const 
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wc = w * 64;
   const int64_t n0 = (int64_t)tn * TM;
-  const bool rok = n0 + lane < a.N;  // this lane's point exists
-  const float *tabr = tab + (int64_t)rl * a.tab_stride;
-  const uint32_t *ytile = D.ytile + (int64_t)tn * a.s;  // y_j(n0) for every j
+  const __amdgpu_buffer_rsrc_t trs = raw_rsrc(tab + (int64_t)rl * a.tab_stride, (uint32_t)(a.tab_stride * 4));
+  const uint32_t *ytile = D.ytile + (int64_t)tn * a.s;  // aoff_j XOR y_j(n0) for every j
 
   // Only wave w reads columns [wc, wc + 64) of the tile, so its B operands come
   // straight from A into registers, one step ahead.  Element e < TK of a lane:
-  // row k0 + brow(e), column bcol(e) of the tile, in the layout of the MFMA
-  // (FP32 32x32x2: e = kk + c; BF16 32x32x16: e = kc + 8 c + q).
-  auto brow = [&](int e) {
-    return PREC == QMC_FP32 ? (e & ~1) + (lane >> 5) : (e & ~15) + 8 * (lane >> 5) + (e & 7);
-  };
+  // row k0 + brow(e) + bh, column colc[bblk(e)] (FP32 32x32x2: e = kk + c,
+  // bh = lane / 32; BF16 32x32x16: e = kc + 8 c + q, bh = 8 (lane / 32)).
+  // Columns past t read column t - 1 (their outputs are dropped); rows past s
+  // read zero (the step's buffer ends at row s).
+  auto brow = [&](int e) { return PREC == QMC_FP32 ? (e & ~1) : (e & ~15) + (e & 7); };
   auto bblk = [&](int e) { return PREC == QMC_FP32 ? (e & 1) : ((e >> 3) & 1); };
-  // columns past t read column t - 1 (their outputs are dropped); rows past s
-  // read row s - 1 (their point values are zero)
-  int colc[2];
+  const int bh = PREC == QMC_FP32 ? (lane >> 5) : 8 * (lane >> 5);
+  uint32_t boff[2];  // byte offset of this lane's element in row k0 of the step
 #pragma unroll
-  for (int c = 0; c < 2; ++c) colc[c] = min(ct * TN + wc + 32 * c + (lane & 31), a.t - 1);
+  for (int c = 0; c < 2; ++c)
+    boff[c] = (uint32_t)(((int64_t)bh * a.lda + min(ct * TN + wc + 32 * c + (lane & 31), a.t - 1)) * 4);
 
   // Step k0: wave w gathers coordinates k0 + KPW w + q (q < KPW) of the 64
-  // points (lane = point).  The validity of a gathered value is applied when it
-  // is stored, so the gathers stay in flight during the products.
-  uint32_t yl[KPW], yt[KPW];  // y_j(lane) and y_j(n0) of the next coordinates to gather
+  // points (lane = point); a value's byte offset is 4 (ytile_j XOR ylo_j(lane)).
+  // Coordinates past s gather coordinate s - 1 (its rows of A read zero), points
+  // past N gather valid values (their outputs are dropped).
+  uint32_t yl[KPW], yt[KPW];  // index words of the next coordinates to gather
   float xv[KPW];
   auto load_index = [&](int k0) {
 #pragma unroll
@@ -98,22 +108,17 @@ __global__ __launch_bounds__(256) void alg4_kernel(Alg4Args a, DevSpec D, const 
   };
   auto load_values = [&](int k0, float (&b)[TK]) {
 #pragma unroll
-    for (int q = 0; q < KPW; ++q) {
-      const int jc = min(k0 + KPW * w + q, a.s - 1);
-      const int nb = D.nbj[jc];
-      const uint32_t msk = nb >= 32 ? 0xffffffffu : ((1u << nb) - 1u);
-      xv[q] = tabr[D.soff[jc] + ((yt[q] ^ yl[q]) & msk)];
-    }
+    for (int q = 0; q < KPW; ++q) xv[q] = load_f32(trs, (yt[q] ^ yl[q]) << 2);
+    const int64_t left = (int64_t)a.s - k0;  // rows of A from row k0 on
+    const int64_t want = ((left - 1) * a.lda + a.t) * 4;
+    const uint32_t bytes = left <= 0 ? 0u : want > 0xffffffffll ? 0xffffffffu : (uint32_t)want;
+    const __amdgpu_buffer_rsrc_t ars = raw_rsrc(left <= 0 ? A : A + (int64_t)k0 * a.lda, bytes);
 #pragma unroll
-    for (int e = 0; e < TK; ++e) {
-      const float *row = A + (int64_t)min(k0 + brow(e), a.s - 1) * a.lda;
-      b[e] = row[colc[bblk(e)]];
-    }
+    for (int e = 0; e < TK; ++e) b[e] = load_f32(ars, (uint32_t)(brow(e) * a.lda * 4) + boff[bblk(e)]);
   };
-  auto store_x = [&](int k0, float *xs) {
+  auto store_x = [&](float *xs) {
 #pragma unroll
-    for (int q = 0; q < KPW; ++q)
-      xs[lane * XPAD + KPW * w + q] = (rok && k0 + KPW * w + q < a.s) ? xv[q] : 0.f;
+    for (int q = 0; q < KPW; ++q) xs[lane * XPAD + KPW * w + q] = xv[q];
   };
 
   f32x16 acc[2][2];
@@ -140,7 +145,7 @@ __global__ __launch_bounds__(256) void alg4_kernel(Alg4Args a, DevSpec D, const 
 #pragma unroll
       for (int kc = 0; kc < TK; kc += 16) {
         const int kq = kc + 8 * (lane >> 5);
-        bf16x8 xh[2], xl[2], bh[2], bl[2];
+        bf16x8 xh[2], xl[2], bh8[2], bl8[2];
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
 #pragma unroll
@@ -154,43 +159,42 @@ __global__ __launch_bounds__(256) void alg4_kernel(Alg4Args a, DevSpec D, const 
           for (int c = 0; c < 2; ++c) {
             const float v = b[kc + 8 * c + q];
             const __bf16 hi = (__bf16)v;
-            bh[c][q] = hi;
-            bl[c][q] = (__bf16)(v - (float)hi);
+            bh8[c][q] = hi;
+            bl8[c][q] = (__bf16)(v - (float)hi);
           }
         }
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
           for (int c = 0; c < 2; ++c) {
-            acc[i][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xl[i], bh[c], acc[i][c], 0, 0, 0);
-            acc[i][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[i], bl[c], acc[i][c], 0, 0, 0);
-            acc[i][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[i], bh[c], acc[i][c], 0, 0, 0);
+            acc[i][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xl[i], bh8[c], acc[i][c], 0, 0, 0);
+            acc[i][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[i], bl8[c], acc[i][c], 0, 0, 0);
+            acc[i][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[i], bh8[c], acc[i][c], 0, 0, 0);
           }
       }
     }
   };
-  // one step: the next step's loads are issued before this step's products;
-  // one barrier per step (the X tile is double-buffered)
+  // one step, without branches: the next step's gathers and rows of A and the
+  // index words of the step after are issued before this step's products; one
+  // barrier per step (the X tile is double-buffered)
   auto step = [&](int k0, const float (&bcur)[TK], float (&bnext)[TK], const float *xcur, float *xnext) {
-    const bool more = k0 + TK < a.s;
-    if (more) {
-      load_values(k0 + TK, bnext);
-      if (k0 + 2 * TK < a.s) load_index(k0 + 2 * TK);
-    }
+    load_values(k0 + TK, bnext);
+    load_index(k0 + 2 * TK);
     products(xcur, bcur);
-    if (more) store_x(k0 + TK, xnext);
+    store_x(xnext);
     __syncthreads();
   };
 
   float b0[TK], b1[TK];
   load_index(0);
   load_values(0, b0);
-  if (TK < a.s) load_index(TK);
-  store_x(0, Xs[0]);
+  load_index(TK);
+  store_x(Xs[0]);
   __syncthreads();
+  // steps past s multiply zero rows of A
   for (int k0 = 0; k0 < a.s; k0 += 2 * TK) {
     step(k0, b0, b1, Xs[0], Xs[1]);
-    if (k0 + TK < a.s) step(k0 + TK, b1, b0, Xs[1], Xs[0]);
+    step(k0 + TK, b1, b0, Xs[1], Xs[0]);
   }
 
   // epilogue: acc[i][c][v] is element (32 i + 8 (v / 4) + 4 (lane / 32) + v % 4,
@@ -277,9 +281,13 @@ static void launch_m(int mode, int gf, dim3 grid, hipStream_t st, const Alg4Args
 }  // namespace
 
 // ylo[j][r] = y_j(r) for r < 64 (rows past N: digits that do not exist are
-// dropped), ytile[h][j] = y_j(64 h) for h < ceil(N / 64).
+// dropped) and ytile[h][j] = aoff_j XOR y_j(64 h) for h < ceil(N / 64), each
+// word restricted to its first n_j digits.  aoff_j, the start of coordinate j's
+// table, is a multiple of n_j, so aoff_j XOR y = aoff_j + y for y < n_j.
 __global__ __launch_bounds__(256) void alg4_index_kernel(int32_t m, int32_t s, int64_t ntiles,
                                                          const uint32_t *__restrict__ gen,
+                                                         const int32_t *__restrict__ nbj,
+                                                         const uint32_t *__restrict__ aoff,
                                                          uint32_t *__restrict__ ylo,
                                                          uint32_t *__restrict__ ytile) {
   const int64_t nlo = (int64_t)64 * s, total = nlo + ntiles * s;
@@ -290,12 +298,14 @@ __global__ __launch_bounds__(256) void alg4_index_kernel(int32_t m, int32_t s, i
       const int64_t j = e >> 6;
       const uint32_t *col = gen + j * m;
       for (uint32_t b = (uint32_t)(e & 63) & lowmask; b; b &= b - 1u) y ^= col[__builtin_ctz(b)];
-      ylo[e] = y;
+      const int nb = nbj[j];
+      ylo[e] = nb >= 32 ? y : y & ((1u << nb) - 1u);
     } else {
       const int64_t h = (e - nlo) / s, j = (e - nlo) - h * s;
       const uint32_t *col = gen + j * m;
       for (uint32_t b = (uint32_t)h; b; b &= b - 1u) y ^= col[6 + __builtin_ctz(b)];
-      ytile[e - nlo] = y;
+      const int nb = nbj[j];
+      ytile[e - nlo] = aoff[j] ^ (nb >= 32 ? y : y & ((1u << nb) - 1u));
     }
   }
 }
@@ -306,12 +316,12 @@ int64_t alg4_index_words(const Geometry &G) { return (64 + alg4_point_tiles(G)) 
 
 int alg4_col_tiles(int t) { return (int)ceil_div(t, TN); }
 
-hipError_t launch_alg4_index(const Geometry &G, const uint32_t *gen, uint32_t *ylo, uint32_t *ytile,
-                             hipStream_t st) {
+hipError_t launch_alg4_index(const Geometry &G, const uint32_t *gen, const int32_t *nbj, const uint32_t *aoff,
+                             uint32_t *ylo, uint32_t *ytile, hipStream_t st) {
   const int64_t total = alg4_index_words(G);
   const int64_t blocks = std::min<int64_t>(ceil_div(total, 256), 65535);
   hipLaunchKernelGGL(alg4_index_kernel, dim3((unsigned)blocks), dim3(256), 0, st, G.m, G.s,
-                     alg4_point_tiles(G), gen, ylo, ytile);
+                     alg4_point_tiles(G), gen, nbj, aoff, ylo, ytile);
   return hipGetLastError();
 }
 
@@ -320,6 +330,8 @@ hipError_t launch_alg4(const Geometry &G, const DevSpec &D, int mode, const qmc_
                        const Alg4Out &o, hipStream_t st) {
   LaunchTimer tm("leaf", st);
   if (mode != kModeStoreY && mode != kModeSum && mode != kModePoint) return hipErrorInvalidValue;
+  // byte offsets of a step's rows of A and of the value tables are 32-bit
+  if (lda > kAlg4MaxLda || D.sample_total * 4 > 0xffffffffll) return hipErrorInvalidValue;
   Alg4Args a{};
   a.m = G.m;
   a.s = G.s;

@@ -437,13 +437,30 @@ qmc_status qmc_points_init(qmc_points *out, const qmc_point_spec *sp) {
   if ((e = hipMalloc(&p->d_soff, (size_t)s * 8)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc"));
   if ((e = hipMemcpy(p->d_soff, soff.data(), (size_t)s * 8, hipMemcpyHostToDevice)) != hipSuccess)
     return cleanup(hip_fail(e, "hipMemcpy"));
-  if (nonperiodic) {  // Algorithm 4: index words from the generating matrices, once
+  if (nonperiodic) {  // Algorithm 4: table starts and index words, once
+    // tables in order of decreasing n_j: every start is a multiple of its n_j
+    std::vector<int> ord(s);
+    for (int j = 0; j < s; ++j) ord[j] = j;
+    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return nbv[x] > nbv[y]; });
+    std::vector<uint32_t> aoff(s);
+    int64_t pos = 0;
+    for (int j : ord) {
+      aoff[j] = (uint32_t)pos;
+      pos += int64_t(1) << nbv[j];
+    }
+    if (pos > kAlg4MaxValues)
+      return cleanup(fail(QMC_EUNSUPPORTED, "Algorithm 4 value tables of %lld values exceed %lld",
+                          (long long)pos, (long long)kAlg4MaxValues));
     const size_t words = (size_t)alg4_index_words(G);
-    if ((e = hipMalloc(&p->d_yidx, words * 4)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc"));
-    uint32_t *ylo = static_cast<uint32_t *>(p->d_yidx), *ytile = ylo + (size_t)64 * s;
-    if ((e = launch_alg4_index(G, static_cast<const uint32_t *>(p->d_gen), ylo, ytile, nullptr)) != hipSuccess ||
+    if ((e = hipMalloc(&p->d_yidx, (words + s) * 4)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc"));
+    uint32_t *ylo = static_cast<uint32_t *>(p->d_yidx), *ytile = ylo + (size_t)64 * s, *daoff = ylo + words;
+    if ((e = hipMemcpy(daoff, aoff.data(), (size_t)s * 4, hipMemcpyHostToDevice)) != hipSuccess)
+      return cleanup(hip_fail(e, "hipMemcpy"));
+    if ((e = launch_alg4_index(G, static_cast<const uint32_t *>(p->d_gen), static_cast<const int32_t *>(p->d_nb),
+                               daoff, ylo, ytile, nullptr)) != hipSuccess ||
         (e = hipDeviceSynchronize()) != hipSuccess)
       return cleanup(hip_fail(e, "Algorithm 4 index tables"));
+    p->D.aoff = daoff;
     p->D.ylo = ylo;
     p->D.ytile = ytile;
   }

@@ -70,8 +70,11 @@ struct DevSpec {
   const double *samples;   // reduced Monte Carlo: [R][sample_total]
   const int64_t *soff;     // [s] start of coordinate j's samples in a replicate
   int64_t sample_total;    // sum_j n_j
-  // Algorithm 4 index words (nets that are not periodic): ylo[j * 64 + r] =
-  // y_j(r) for r < 64, ytile[h * s + j] = y_j(64 h)
+  // Algorithm 4 (nets that are not periodic): aoff[j] = start of coordinate j's
+  // value table, a multiple of n_j; index words restricted to the first n_j
+  // digits, ylo[j * 64 + r] = y_j(r) for r < 64, ytile[h * s + j] =
+  // aoff[j] XOR y_j(64 h)
+  const uint32_t *aoff;
   const uint32_t *ylo;
   const uint32_t *ytile;
 };
@@ -127,7 +130,7 @@ hipError_t launch_point_values(const Geometry &G, const DevSpec &D, int r, int j
 // Algorithm 4 value tables in digit order: T_j[y] = X_j[c] for y < n_j, c the
 // integer of the reduced output digits and y its n_j-digit bit reversal (the
 // digits as the generating matrix produces them); sum_j n_j floats per
-// randomisation, coordinate blocks at DevSpec::soff.
+// randomisation, coordinate j's block at DevSpec::aoff[j].
 hipError_t launch_output_tables(const Geometry &G, const DevSpec &D, int r0, int nr, float *out,
                                 hipStream_t st);
 hipError_t launch_point_matrix(const Geometry &G, const DevSpec &D, int r, float *X, int64_t ldx,
@@ -215,8 +218,10 @@ struct Alg4Out {
 int64_t alg4_point_tiles(const Geometry &G);
 int64_t alg4_index_words(const Geometry &G);  // (64 + tiles) * s
 int alg4_col_tiles(int t);
-hipError_t launch_alg4_index(const Geometry &G, const uint32_t *gen, uint32_t *ylo, uint32_t *ytile,
-                             hipStream_t st);
+constexpr int64_t kAlg4MaxLda = int64_t(1) << 24;     // leading dimension of A
+constexpr int64_t kAlg4MaxValues = int64_t(1) << 30;  // sum_j n_j
+hipError_t launch_alg4_index(const Geometry &G, const uint32_t *gen, const int32_t *nbj, const uint32_t *aoff,
+                             uint32_t *ylo, uint32_t *ytile, hipStream_t st);
 hipError_t launch_alg4(const Geometry &G, const DevSpec &D, int mode, const qmc_integrand &f,
                        int prec, const float *tab, int nr, const float *A, int t, int64_t lda,
                        const Alg4Out &o, hipStream_t st);

@@ -312,7 +312,7 @@ __global__ __launch_bounds__(256) void outvals_kernel(PointConsts G, DevSpec D, 
     const int nb = D.nbj[lo];
     const uint32_t y = (uint32_t)(e - D.soff[lo]);  // digit-order index
     const uint32_t c = nb == 0 ? 0u : __builtin_bitreverse32(y) >> (32 - nb);
-    out[(int64_t)rl * total + e] = (float)value_f64<INVNORM>(G, D, r0 + rl, lo, c, nb);
+    out[(int64_t)rl * total + D.aoff[lo] + y] = (float)value_f64<INVNORM>(G, D, r0 + rl, lo, c, nb);
   }
 }
 
