@@ -31,7 +31,7 @@ def build(force: bool = True) -> str:
 
 
 class _Spec(ct.Structure):
-    _fields_ = [("kind", ct.c_int32), ("m", ct.c_int32), ("s", ct.c_int32),
+    _fields_ = [("b", ct.c_int32), ("kind", ct.c_int32), ("m", ct.c_int32), ("s", ct.c_int32),
                 ("w", ct.POINTER(ct.c_int32)), ("gen", ct.POINTER(ct.c_uint64)),
                 ("rand", ct.c_int32), ("R", ct.c_int32),
                 ("shift", ct.POINTER(ct.c_double)), ("dshift", ct.POINTER(ct.c_uint64)),
@@ -87,7 +87,7 @@ class Spec:
         self.samples = None if samples is None else np.ascontiguousarray(samples, dtype=np.float64)
         self.R = wl.R
         self.m, self.s = wl.m, wl.s
-        self.c = _Spec(kind=wl.kind, m=wl.m, s=wl.s,
+        self.c = _Spec(b=wl.b, kind=wl.kind, m=wl.m, s=wl.s,
                        w=self.w.ctypes.data_as(ct.POINTER(ct.c_int32)),
                        gen=self.gen.ctypes.data_as(ct.POINTER(ct.c_uint64)),
                        rand=wl.rand, R=wl.R,
@@ -106,15 +106,15 @@ def _A64(wl):
 def point_values(wl, r: int, j: int) -> np.ndarray:
     sp = Spec(wl)
     nb = int(wl.m - min(int(wl.w[j]), wl.m))
-    out = np.empty(1 << nb, dtype=np.float64)
-    lib().qo_point_values(ct.byref(sp.c), r, j, _dp(out))
+    out = np.empty(wl.b ** nb, dtype=np.float64)
+    assert lib().qo_point_values(ct.byref(sp.c), r, j, _dp(out)) == 0
     return out
 
 
 def point_matrix_unreduced(wl, r: int = 0) -> np.ndarray:
     sp = Spec(wl)
     X = np.empty((wl.N, wl.s), dtype=np.float64)
-    lib().qo_point_matrix_unreduced(ct.byref(sp.c), r, _dp(X))
+    assert lib().qo_point_matrix_unreduced(ct.byref(sp.c), r, _dp(X)) == 0
     return X
 
 

@@ -29,6 +29,9 @@
  *     x = (2U + 1) 2^-53,  U = (c << (52 - n)) ^ delta;
  *   - the random shift is one IEEE FP64 addition followed by "subtract 1 if the
  *     sum is >= 1";
+ *   - a prime base b > 2 is taken for lattices and reduced Monte Carlo, whose
+ *     values c / b^e are one correctly rounded FP64 division; digital nets,
+ *     polynomial lattices and the digital shift stay base 2;
  *   - the inverse normal map is Wichura's algorithm AS241 (PPND16);
  *   - the integrand is f(y) = h(t^-1 sum_i g(y_i)) with g in {y, cos y,
  *     exp(c y)} and h in {u, max(0, u - K)}; h'(K) is taken as 0;
@@ -54,9 +57,10 @@ enum { QO_MAP_ID = 0, QO_MAP_CENTER = 1, QO_MAP_INVNORM = 2, QO_MAP_TENT = 3 };
 enum { QO_G_ID = 0, QO_G_COS = 1, QO_G_EXP = 2 };
 enum { QO_H_ID = 0, QO_H_CALL = 1 };
 
-/* A point set: base b = 2, N = 2^m points in s dimensions. */
+/* A point set: prime base b, N = b^m points in s dimensions (digital nets and
+ * polynomial lattices: b = 2). */
 typedef struct {
-    int32_t kind, m, s;
+    int32_t b, kind, m, s;
     const int32_t *w;         /* [s] reduction indices, w[0] = 0, non-decreasing */
     const uint64_t *gen;      /* lattice z'_j [s]; poly g'_j bits [s]; net column words [s*m] */
     int32_t rand, R;
@@ -75,10 +79,20 @@ typedef struct {
 
 /* ------------------------------------------------------------ small helpers */
 
+/* e_j = m - min(w_j, m): coordinate j has n_j = b^{e_j} distinct values */
 static int nbits_of(const qo_spec *sp, int j) {
     int w = sp->w[j];
-    return sp->m - (w < sp->m ? w : sp->m);   /* n_j = b^{m - min(w_j, m)} = 2^nbits */
+    return sp->m - (w < sp->m ? w : sp->m);
 }
+
+static uint64_t ipow(uint64_t b, int e) {
+    uint64_t r = 1;
+    for (int i = 0; i < e; ++i) r *= b;
+    return r;
+}
+
+static uint64_t n_of(const qo_spec *sp, int j) { return ipow((uint64_t)sp->b, nbits_of(sp, j)); }
+static int64_t N_of(const qo_spec *sp) { return (int64_t)ipow((uint64_t)sp->b, sp->m); }
 
 /* carry-less product of two F_2[x] polynomials given as bit masks, mod x^nb */
 static uint64_t clmul_mod(uint64_t a, uint64_t b, int nb) {
@@ -147,14 +161,15 @@ static double apply_map(const qo_spec *sp, double x) {
     }
 }
 
-/* Shift then map one coordinate value given as the integer c of c / 2^nb. */
+/* Shift then map one coordinate value given as the integer c of c / b^nb. */
 static double shift_and_map(const qo_spec *sp, int r, int j, uint64_t c, int nb) {
     double x;
-    if (sp->rand == QO_DIGITAL_SHIFT) {
+    if (sp->rand == QO_DIGITAL_SHIFT) {                      /* b = 2 */
         uint64_t U = (c << (52 - nb)) ^ sp->dshift[(size_t)r * sp->s + j];
         x = (double)(2 * U + 1) * 0x1p-53;                  /* exact */
     } else {
-        x = (double)c / (double)(UINT64_C(1) << nb);         /* exact */
+        /* one correctly rounded division (exact for b = 2) */
+        x = (double)c / (double)ipow((uint64_t)sp->b, nb);
         if (sp->rand == QO_RANDOM_SHIFT) {
             x = x + sp->shift[(size_t)r * sp->s + j];        /* one rounding */
             if (x >= 1.0) x = x - 1.0;                       /* exact */
@@ -173,12 +188,12 @@ static double shift_and_map(const qo_spec *sp, int r, int j, uint64_t c, int nb)
  */
 static int64_t iid_offset(const qo_spec *sp, int j) {   /* start of coordinate j's samples */
     int64_t off = 0;
-    for (int i = 0; i < j; ++i) off += (int64_t)1 << nbits_of(sp, i);
+    for (int i = 0; i < j; ++i) off += (int64_t)n_of(sp, i);
     return off;
 }
 
 static uint64_t iid_N(const qo_spec *sp, int i) {       /* N_i, and N_s = 1 past the last */
-    return i >= sp->s ? 1 : (UINT64_C(1) << nbits_of(sp, i));
+    return i >= sp->s ? 1 : n_of(sp, i);
 }
 
 static uint64_t iid_index(const qo_spec *sp, int j, uint64_t n) {
@@ -200,9 +215,9 @@ static double iid_value(const qo_spec *sp, int r, int j, uint64_t index) {
 /* ------------------------------------------------------------ point sets */
 
 /*
- * Integer c_j(rho) of the distinct value c / 2^nb_j of coordinate j at residue
- * rho < 2^nb_j, from the reduced definitions.
- *   lattice (Sec. 1.3):   c = rho * z'_j mod 2^nb
+ * Integer c_j(rho) of the distinct value c / n_j of coordinate j at residue
+ * rho < n_j, from the reduced definitions.
+ *   lattice (Sec. 1.3):   c = rho * z'_j mod n_j, n_j = b^nb
  *   polynomial (Sec. 1.1 with g_j = x^{w_j} g'_j): nu(k g_j / x^m) reduces to
  *                         int(k g'_j mod x^nb) / 2^nb, no digit reversal
  *   net (eq. def:digital with reduced_genmat_net2): digits y_p = sum_q
@@ -211,7 +226,7 @@ static double iid_value(const qo_spec *sp, int r, int j, uint64_t index) {
 static uint64_t reduced_int(const qo_spec *sp, int j, uint64_t rho) {
     int nb = nbits_of(sp, j);
     uint64_t mask = nb >= 64 ? ~UINT64_C(0) : ((UINT64_C(1) << nb) - 1);
-    if (sp->kind == QO_LATTICE) return (rho * sp->gen[j]) & mask;
+    if (sp->kind == QO_LATTICE) return (uint64_t)(((unsigned __int128)rho * sp->gen[j]) % n_of(sp, j));
     if (sp->kind == QO_POLY_LATTICE) return clmul_mod(rho, sp->gen[j], nb);
     uint64_t y = 0;   /* digital net: XOR of the columns selected by the digits of rho */
     for (int q = 0; q < sp->m; ++q)
@@ -220,10 +235,21 @@ static uint64_t reduced_int(const qo_spec *sp, int j, uint64_t rho) {
     return bitrev(y, nb);
 }
 
+/* The bases taken here: b = 2 for every kind; a prime b > 2 for lattices and
+ * reduced Monte Carlo, without a digital shift. */
+static int base_supported(const qo_spec *sp) {
+    if (sp->b == 2) return 1;
+    if (sp->b < 2) return 0;
+    for (int d = 2; d * d <= sp->b; ++d)
+        if (sp->b % d == 0) return 0;
+    return (sp->kind == QO_LATTICE || sp->kind == QO_IID) && sp->rand != QO_DIGITAL_SHIFT;
+}
+
 /* Distinct values X_j[rho], rho < n_j, of coordinate j for shift r (FP64). */
 int qo_point_values(const qo_spec *sp, int r, int j, double *out) {
+    if (!base_supported(sp)) return 3;
     int nb = nbits_of(sp, j);
-    uint64_t n = UINT64_C(1) << nb;
+    uint64_t n = n_of(sp, j);
     for (uint64_t rho = 0; rho < n; ++rho)
         out[rho] = sp->kind == QO_IID ? iid_value(sp, r, j, rho)
                                       : shift_and_map(sp, r, j, reduced_int(sp, j, rho), nb);
@@ -234,16 +260,16 @@ int qo_point_values(const qo_spec *sp, int r, int j, double *out) {
  * Point k, coordinate j, from the UNREDUCED definitions (used only by the
  * dense check): lattice {k b^{w_j} z'_j / b^m}; polynomial nu(k(x) x^{w_j}
  * g'_j(x) / x^m); net with the full m x m reduced matrix applied to all m
- * digits of k.  Expressed as an integer over 2^m.
+ * digits of k.  Expressed as an integer over N = b^m.
  */
 static uint64_t unreduced_int_over_N(const qo_spec *sp, int j, uint64_t k) {
     int m = sp->m, w = sp->w[j];
-    uint64_t maskm = (UINT64_C(1) << m) - 1;
     if (sp->kind == QO_LATTICE) {
         /* z_j = b^{w_j} z'_j; when w_j >= m the component is a multiple of N */
         if (w >= m) return 0;
-        uint64_t z = sp->gen[j] << w;
-        return (k * z) & maskm;
+        uint64_t N = (uint64_t)N_of(sp);
+        uint64_t z = (uint64_t)(((unsigned __int128)ipow((uint64_t)sp->b, w) * sp->gen[j]) % N);
+        return (uint64_t)(((unsigned __int128)k * z) % N);
     }
     if (sp->kind == QO_POLY_LATTICE) {
         if (w >= m) return 0;
@@ -263,7 +289,8 @@ static uint64_t unreduced_int_over_N(const qo_spec *sp, int j, uint64_t k) {
 
 /* Full N x s point matrix (row k = point x_k) from the unreduced definitions. */
 int qo_point_matrix_unreduced(const qo_spec *sp, int r, double *X) {
-    int64_t N = (int64_t)1 << sp->m;
+    if (!base_supported(sp)) return 3;
+    int64_t N = N_of(sp);
     int s = sp->s;
 #pragma omp parallel for schedule(static)
     for (int64_t k = 0; k < N; ++k) {
@@ -273,7 +300,7 @@ int qo_point_matrix_unreduced(const qo_spec *sp, int r, double *X) {
                 continue;
             }
             uint64_t cN = unreduced_int_over_N(sp, j, (uint64_t)k);
-            /* value cN / 2^m; shift_and_map takes c / 2^nb, so pass nb = m */
+            /* value cN / b^m; shift_and_map takes c / b^nb, so pass nb = m */
             X[k * s + j] = shift_and_map(sp, r, j, cN, sp->m);
         }
     }
@@ -312,15 +339,16 @@ static int replicates(const qo_spec *sp) {
  */
 int qo_alg1(const qo_spec *sp, int r, const double *A, int t, int i0, int i1,
             double *P, int64_t *nmadd) {
+    if (!base_supported(sp)) return 3;
     int tb = i1 - i0;
     int64_t rows = 1;                 /* P_{s*+1} = 0 (1 x tb), w_{s+1} := m */
     for (int i = 0; i < tb; ++i) P[i] = 0.0;
-    double *v = (double *)malloc(sizeof(double) * ((size_t)1 << sp->m));
+    double *v = (double *)malloc(sizeof(double) * (size_t)N_of(sp));
     if (!v) return 1;
     int64_t count = 0;
     for (int j = sp->s - 1; j >= 0; --j) {
         if (column_is_zero(sp, j)) continue;
-        int64_t nj = (int64_t)1 << nbits_of(sp, j);
+        int64_t nj = (int64_t)n_of(sp, j);
         /* tile: rows [rows, nj) repeat rows [0, rows) */
 #pragma omp parallel for schedule(static)
         for (int64_t rho = rows; rho < nj; ++rho)
@@ -334,7 +362,7 @@ int qo_alg1(const qo_spec *sp, int r, const double *A, int t, int i0, int i1,
         if (sp->w[j] < sp->m) count += nj * tb;
     }
     /* if every column was zero, P is still one row: tile to N rows */
-    int64_t N = (int64_t)1 << sp->m;
+    int64_t N = N_of(sp);
     for (int64_t rho = rows; rho < N; ++rho) memcpy(P + rho * tb, P + (rho % rows) * tb, sizeof(double) * tb);
     free(v);
     if (nmadd) *nmadd += count;
@@ -460,7 +488,7 @@ static int block_width(int t) { return t < 64 ? t : 64; }
  */
 static int point_means(const qo_spec *sp, int r, const double *A, int t,
                        const qo_integrand *f, double *u, double *P, int64_t *nmadd) {
-    int64_t N = (int64_t)1 << sp->m;
+    int64_t N = N_of(sp);
     for (int64_t k = 0; k < N; ++k) u[k] = 0.0;
     int tb = block_width(t);
     for (int i0 = 0; i0 < t; i0 += tb) {
@@ -477,7 +505,7 @@ static int point_means(const qo_spec *sp, int r, const double *A, int t,
 /* Q[r] = N^-1 sum_k h(u_k) for every shift r (eq. QMC-rule). */
 int qo_estimate(const qo_spec *sp, const double *A, int t, const qo_integrand *f,
                 double *Q, int64_t *nmadd) {
-    int64_t N = (int64_t)1 << sp->m;
+    int64_t N = N_of(sp);
     int tb = block_width(t);
     double *P = (double *)malloc(sizeof(double) * (size_t)N * tb);
     double *u = (double *)malloc(sizeof(double) * (size_t)N);
@@ -503,7 +531,7 @@ int qo_estimate(const qo_spec *sp, const double *A, int t, const qo_integrand *f
 int qo_estimate_grad(const qo_spec *sp, const double *A, int t, const qo_integrand *f,
                      double *Q, double *dA) {
     if (!net_is_periodic(sp)) return 2;  /* the fold below needs periodic tables */
-    int64_t N = (int64_t)1 << sp->m;
+    int64_t N = N_of(sp);
     int s = sp->s, tb = block_width(t);
     double *P = (double *)malloc(sizeof(double) * (size_t)N * tb);
     double *u = (double *)malloc(sizeof(double) * (size_t)N);
@@ -518,7 +546,7 @@ int qo_estimate_grad(const qo_spec *sp, const double *A, int t, const qo_integra
         double *dAr = dA + (size_t)r * s * t;
         for (int i0 = 0; i0 < t; i0 += tb) {
             int i1 = i0 + tb < t ? i0 + tb : t, w = i1 - i0;
-            qo_alg1(sp, r, A, t, i0, i1, P, NULL);
+            if (qo_alg1(sp, r, A, t, i0, i1, P, NULL)) { free(P); free(u); free(hv); free(v); return 1; }
             /* G in place of Y */
 #pragma omp parallel for schedule(static)
             for (int64_t k = 0; k < N; ++k) {
@@ -527,7 +555,7 @@ int qo_estimate_grad(const qo_spec *sp, const double *A, int t, const qo_integra
             }
             int64_t rows = N;
             for (int j = 0; j < s; ++j) {
-                int64_t nj = (int64_t)1 << nbits_of(sp, j);
+                int64_t nj = (int64_t)n_of(sp, j);
                 /* fold: S[rho] = sum_c S[rho + c nj], rho < nj */
                 if (nj < rows) {
                     int64_t reps = rows / nj;
@@ -554,7 +582,7 @@ int qo_estimate_grad(const qo_spec *sp, const double *A, int t, const qo_integra
 
 /* Y = X A for one shift by Algorithm 1 over all columns (column blocks of 64). */
 int qo_reduced_matvec(const qo_spec *sp, int r, const double *A, int t, double *Y, int64_t *nmadd) {
-    int64_t N = (int64_t)1 << sp->m;
+    int64_t N = N_of(sp);
     int tb = block_width(t);
     double *P = (double *)malloc(sizeof(double) * (size_t)N * tb);
     if (!P) return 1;

@@ -68,7 +68,7 @@ class Workload:
         return np.ascontiguousarray(self.A64.astype(np.float32))
 
     def nbits(self) -> np.ndarray:
-        """m - min(w_j, m): coordinate j takes 2**nbits[j] distinct values."""
+        """m - min(w_j, m): coordinate j takes b**nbits[j] distinct values."""
         return (self.m - np.minimum(self.w, self.m)).astype(np.int64)
 
 
@@ -77,6 +77,17 @@ class Workload:
 def w_log2(s: int, cap: int) -> np.ndarray:
     """w_j = min(cap, floor(log2(j+1))), j = 0..s-1 (exact integer arithmetic)."""
     return np.array([min(cap, (j + 1).bit_length() - 1) for j in range(s)], dtype=np.int32)
+
+
+def w_logb(s: int, cap: int, b: int) -> np.ndarray:
+    """w_j = min(cap, floor(log_b(j+1))), j = 0..s-1: the largest q with b^q <= j+1."""
+    out = []
+    for j in range(s):
+        q = 0
+        while b ** (q + 1) <= j + 1:
+            q += 1
+        out.append(min(cap, q))
+    return np.array(out, dtype=np.int32)
 
 
 def w_log2_pow(s: int, cap: int, num: int, den: int) -> np.ndarray:
@@ -93,12 +104,17 @@ def w_log2_pow(s: int, cap: int, num: int, den: int) -> np.ndarray:
 
 # ---------------------------------------------------------------- generators
 
-def draw_lattice(rng: np.random.Generator, nb: np.ndarray) -> np.ndarray:
-    """z'_j uniform over the odd integers in [1, 2^nb_j); z'_j = 1 when nb_j = 0."""
+def draw_lattice(rng: np.random.Generator, nb: np.ndarray, b: int = 2) -> np.ndarray:
+    """z'_j uniform over the units modulo b^nb_j (the integers in [1, b^nb_j)
+    not divisible by b; for b = 2 the odd ones); z'_j = 1 when nb_j = 0."""
     z = np.ones(len(nb), dtype=np.uint64)
     for j, n in enumerate(nb):
         if n >= 1:
-            z[j] = np.uint64(2 * int(rng.integers(0, 1 << (int(n) - 1))) + 1)
+            if b == 2:
+                z[j] = np.uint64(2 * int(rng.integers(0, 1 << (int(n) - 1))) + 1)
+            else:
+                q = int(rng.integers(0, b ** (int(n) - 1)))
+                z[j] = np.uint64(b * q + int(rng.integers(1, b)))
     return z
 
 
@@ -128,12 +144,12 @@ def draw_net_lower(rng: np.random.Generator, s: int, m: int) -> np.ndarray:
     return words
 
 
-def draw_iid_samples(rng: np.random.Generator, R: int, nb: np.ndarray) -> np.ndarray:
+def draw_iid_samples(rng: np.random.Generator, R: int, nb: np.ndarray, b: int = 2) -> np.ndarray:
     """Reduced Monte Carlo inputs: for each of R replicates and each coordinate j,
-    2^nb_j independent uniforms, coordinate blocks contiguous: [R, sum_j 2^nb_j].
+    b^nb_j independent uniforms, coordinate blocks contiguous: [R, sum_j b^nb_j].
     Each value is (k + 1/2) 2^-53 with k uniform below 2^53: exact in FP64 and
     strictly inside (0, 1), so the inverse-normal map is always finite."""
-    total = int(sum(1 << int(n) for n in nb))
+    total = int(sum(b ** int(n) for n in nb))
     k = rng.integers(0, 1 << 53, size=(R, total), dtype=np.uint64)
     return (k.astype(np.float64) + 0.5) * 2.0 ** -53
 
@@ -304,13 +320,15 @@ def make_config(c: int, seed: int | None = None, *, m: int | None = None, s: int
 
 def make_custom(*, kind: int, m: int, s: int, t: int, w: np.ndarray, rand: int = NO_SHIFT,
                 R: int = 1, map: int = MAP_ID, g: int = G_COS, c: float = 1.0, h: int = H_ID,
-                K: float = 0.0, A_scale: float = 1.0, seed: int = 7, net: str = "lower") -> Workload:
-    """A small random workload of any shape (tests): N(0,1)*A_scale matrix, random generators."""
+                K: float = 0.0, A_scale: float = 1.0, seed: int = 7, net: str = "lower",
+                b: int = 2) -> Workload:
+    """A small random workload of any shape (tests): N(0,1)*A_scale matrix, random
+    generators; a prime base b > 2 is for lattices and reduced Monte Carlo."""
     rng = np.random.default_rng(seed)
     w = np.asarray(w, dtype=np.int32)
     nb = (m - np.minimum(w, m)).astype(np.int64)
     if kind == LATTICE:
-        gen = draw_lattice(rng, nb)
+        gen = draw_lattice(rng, nb, b)
     elif kind == POLY_LATTICE:
         gen = draw_poly(rng, nb)
     elif kind == IID:
@@ -324,13 +342,13 @@ def make_custom(*, kind: int, m: int, s: int, t: int, w: np.ndarray, rand: int =
     if kind == IID:
         if rand != NO_SHIFT:
             raise ValueError("reduced Monte Carlo takes no shift: R counts independent replicates")
-        samples = draw_iid_samples(rng, R, nb)
+        samples = draw_iid_samples(rng, R, nb, b)
     elif rand == RANDOM_SHIFT:
         shift = rng.random((R, s))
     elif rand == DIGITAL_SHIFT:
         dshift = rng.integers(0, 1 << 52, size=(R, s), dtype=np.uint64)
     else:
         R = 1
-    return Workload(name="custom", kind=kind, b=2, m=m, s=s, t=t, w=w, gen=gen, rand=rand,
+    return Workload(name="custom", kind=kind, b=b, m=m, s=s, t=t, w=w, gen=gen, rand=rand,
                     R=R, shift=shift, dshift=dshift, map=map, A64=np.ascontiguousarray(A64),
                     g=g, c=c, h=h, K=K, samples=samples)

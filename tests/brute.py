@@ -4,7 +4,7 @@ Independent of the C oracle: exact rational arithmetic with Python integers
 and Fractions, explicit digit vectors, explicit F_2 matrices and polynomials.
 Used to pin the oracle's point tables.
 
-  lattice      Sec. 1.1 / 1.3: x_k = {k z / N}, z_j = b^{w_j} z'_j
+  lattice      Sec. 1.1 / 1.3: x_k = {k z / N}, z_j = b^{w_j} z'_j, N = b^m (any prime b)
   polynomial   Sec. 1.1: x_k = nu(k(x) g_j(x) / x^m), g_j = x^{w_j} g'_j
   digital net  eq. def:digital with the reduced matrices of eq.
                reduced_genmat_net2: last min(w_j, m) rows of C^{(j)} set to 0
@@ -58,10 +58,10 @@ def poly_mul_mod2(a: list[int], b: list[int]) -> list[int]:
 
 def unshifted_value(wl, k: int, j: int) -> Fraction:
     """The unreduced point definition, as an exact fraction in [0, 1)."""
-    m, N = wl.m, 1 << wl.m
+    m, N = wl.m, wl.b ** wl.m
     w = int(wl.w[j])
     if wl.kind == LATTICE:
-        z = (2 ** w) * int(wl.gen[j])
+        z = (wl.b ** w) * int(wl.gen[j])
         return Fraction((k * z) % N, N)
     if wl.kind == POLY_LATTICE:
         gp = digits(int(wl.gen[j]), 64)
@@ -84,11 +84,11 @@ def digital_shift(x: Fraction, delta: int) -> float:
 
 
 def randpts_index(wl, n: int, j: int) -> int:
-    """eq. randpts: with N_i = 2^{m - min(w_i, m)}, N_{s+1} = 1, write
+    """eq. randpts: with N_i = b^{m - min(w_i, m)}, N_{s+1} = 1, write
     n = m_1 N_2 + m_2 N_3 + ... + m_s N_{s+1} (0 <= m_i < N_i / N_{i+1}, top
     digit first); coordinate j takes sample m_j N_{j+1} + ... + m_s N_{s+1}."""
     m, s = wl.m, wl.s
-    Nn = [1 << (m - min(int(wl.w[i]), m)) for i in range(s)] + [1]
+    Nn = [wl.b ** (m - min(int(wl.w[i]), m)) for i in range(s)] + [1]
     rest, dig = n, []
     for i in range(s):
         dig.append(rest // Nn[i + 1])
@@ -101,7 +101,7 @@ def value(wl, r: int, k: int, j: int) -> float:
     """Point k, coordinate j, shift r, after the map (FP64)."""
     if wl.kind == IID:
         nb = [wl.m - min(int(wl.w[i]), wl.m) for i in range(wl.s)]
-        off = sum(1 << nb[i] for i in range(j))
+        off = sum(wl.b ** nb[i] for i in range(j))
         v = float(wl.samples[r, off + randpts_index(wl, k, j)])
     elif wl.rand == DIGITAL_SHIFT:
         v = digital_shift(unshifted_value(wl, k, j), int(wl.dshift[r, j]))
@@ -121,5 +121,5 @@ def value(wl, r: int, k: int, j: int) -> float:
 
 
 def point_matrix(wl, r: int = 0) -> np.ndarray:
-    N = 1 << wl.m
+    N = wl.b ** wl.m
     return np.array([[value(wl, r, k, j) for j in range(wl.s)] for k in range(N)])

@@ -550,3 +550,144 @@ def test_alg4_estimate_matches_definition(oracle_lib):
         u = np.mean(np.exp(wl.c * Y), axis=1)
         ref = float(np.mean(np.maximum(u - wl.K, 0.0)))
         assert abs(Q[r] - ref) <= 1e-13 * max(abs(ref), 1e-300)
+
+
+# ------------------------------------------------------------------ prime base b > 2
+
+BASES = [(3, 5), (5, 3), (7, 3)]   # (b, m): N = 243, 125, 343
+
+
+def small_b(b, m, rand, mp=I.MAP_ID, s=10, t=5, R=2, seed=3, kind=I.LATTICE, g=I.G_COS, h=I.H_ID, K=0.0):
+    w = I.w_logb(s, m + 1, b)  # includes coordinates with w_j >= m
+    return I.make_custom(kind=kind, m=m, s=s, t=t, w=w, rand=rand, R=R, map=mp, g=g, h=h, K=K,
+                         seed=seed, b=b)
+
+
+@pytest.mark.parametrize("b,m", BASES)
+@pytest.mark.parametrize("rand", [I.NO_SHIFT, I.RANDOM_SHIFT])
+@pytest.mark.parametrize("mp", [I.MAP_ID, I.MAP_CENTER, I.MAP_TENT])
+def test_base_b_tables_match_unreduced_definition(oracle_lib, b, m, rand, mp):
+    """Sec. 1.3 in base b: the reduced table of coordinate j (n_j = b^{m -
+    min(w_j, m)} values, indexed by k mod n_j) reproduces the unreduced lattice
+    {k b^{w_j} z'_j / b^m} bit for bit in FP64 for every k."""
+    O = oracle_lib
+    wl = small_b(b, m, rand, mp)
+    for r in range(wl.R):
+        X = brute.point_matrix(wl, r)
+        for j in range(wl.s):
+            vals = O.point_values(wl, r, j)
+            assert len(vals) == b ** (wl.m - min(int(wl.w[j]), wl.m))
+            np.testing.assert_array_equal(vals[np.arange(wl.N) % len(vals)], X[:, j])
+
+
+@pytest.mark.parametrize("b,m", BASES)
+def test_base_b_value_multiplicity(oracle_lib, b, m):
+    """Sec. 1.3 in base b: coordinate j takes each value c / b^{m-min(w_j,m)}
+    exactly b^{min(w_j,m)} times over the N = b^m points; j > s* gives zeros."""
+    O = oracle_lib
+    wl = small_b(b, m, I.NO_SHIFT, s=14)
+    X = brute.point_matrix(wl, 0)
+    for j in range(wl.s):
+        n = b ** (wl.m - min(int(wl.w[j]), wl.m))
+        c = np.round(X[:, j] * n).astype(np.int64)
+        assert np.all(c / n == X[:, j])
+        assert np.all(np.bincount(c, minlength=n) == b ** min(int(wl.w[j]), wl.m))
+        if int(wl.w[j]) >= wl.m:
+            assert np.all(O.point_values(wl, 0, j) == 0.0)
+
+
+def test_base3_example_golden(oracle_lib):
+    """The base-3 lattice worked by hand in tests/golden/base3_lattice_example.txt
+    (b = 3, m = 2, w = (0, 1), z' = (1, 2)): the oracle's reduced tables, indexed
+    by k mod n_j, give x_{k,1} = c_1 / 9 and x_{k,2} = c_2 / 3."""
+    import dataclasses
+    O = oracle_lib
+    rows = [list(map(int, ln.split())) for ln in open(os.path.join(GOLDEN, "base3_lattice_example.txt"))
+            if ln.strip() and not ln.startswith("#")]
+    wl = I.make_custom(kind=I.LATTICE, m=2, s=2, t=1, w=[0, 1], seed=11, b=3)
+    wl = dataclasses.replace(wl, gen=np.array([1, 2], dtype=np.uint64))
+    v1, v2 = O.point_values(wl, 0, 0), O.point_values(wl, 0, 1)
+    assert len(v1) == 9 and len(v2) == 3
+    assert len(rows) == 9
+    for k, c1, c2 in rows:
+        assert v1[k % 9] == c1 / 9 and v2[k % 3] == c2 / 3
+
+
+@pytest.mark.parametrize("b,m", BASES)
+@pytest.mark.parametrize("rand", [I.NO_SHIFT, I.RANDOM_SHIFT])
+def test_base_b_alg1_equals_dense(oracle_lib, b, m, rand):
+    """Algorithm 1 with base-b tiling (P is tiled to n_j = b^e rows) agrees with
+    the dense product of the unreduced base-b lattice to 1e-13 relative."""
+    O = oracle_lib
+    for seed in range(2):
+        mp = I.MAP_INVNORM if rand == I.RANDOM_SHIFT and seed == 1 else I.MAP_ID
+        wl = small_b(b, m, rand, mp, s=17, t=11, seed=seed)
+        for r in range(wl.R):
+            X = O.point_matrix_unreduced(wl, r)
+            Yd = O.dense_matvec(X, wl.A.astype(np.float64))
+            Yr = O.reduced_matvec(wl, r)
+            assert np.linalg.norm(Yr - Yd) <= 1e-13 * np.linalg.norm(Yd)
+
+
+@pytest.mark.parametrize("b,m", BASES)
+@pytest.mark.parametrize("rand", [I.NO_SHIFT, I.RANDOM_SHIFT])
+def test_base_b_linear_integrand_exact(oracle_lib, b, m, rand):
+    """eq. QMC-rule with g = h = id in base b: the values c / n (c < n, each
+    b^{w_j} times) average to (n-1)/(2n), and after the random shift
+    {x + Delta} to (n - 1 + 2{n Delta}) / (2n), n = b^e."""
+    O = oracle_lib
+    wl = small_b(b, m, rand, s=30, t=7, R=3, g=I.G_ID, h=I.H_ID)
+    Q, _ = O.estimate(wl)
+    A = wl.A.astype(np.float64)
+    for r in range(wl.R):
+        mu = []
+        for j in range(wl.s):
+            n = b ** (wl.m - min(int(wl.w[j]), wl.m))
+            f = (n * float(wl.shift[r, j])) % 1.0 if rand == I.RANDOM_SHIFT else 0.0
+            mu.append((n - 1 + 2 * f) / (2 * n))
+        ref = float(np.mean(np.array(mu) @ A))
+        assert abs(Q[r] - ref) <= 1e-13 * max(1.0, abs(ref))
+
+
+@pytest.mark.parametrize("b,m", BASES)
+def test_base_b_gradient_equals_dense(oracle_lib, b, m):
+    """The residue-class fold of dQ/dA with base-b classes (n_j = b^e) equals
+    the dense X^T G of the unreduced base-b lattice."""
+    O = oracle_lib
+    wl = small_b(b, m, I.RANDOM_SHIFT, s=13, t=6, g=I.G_EXP, h=I.H_CALL, K=1.0)
+    wl.c = 0.3
+    Q, dA = O.estimate_grad(wl)
+    A = wl.A.astype(np.float64)
+    for r in range(wl.R):
+        ref = _dense_grad(wl, A, O.point_matrix_unreduced(wl, r), r)
+        assert np.linalg.norm(dA[r] - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+def test_base3_reduced_monte_carlo_digits(oracle_lib):
+    """Sec. 4, eq. randpts in base 3: N_j = 3^{m - w_j}; the mixed-radix digits
+    of n (brute force, top digit first) select the sample, which equals the
+    oracle's table at n mod N_j, and Algorithm 1 on those tables is the dense
+    product."""
+    O = oracle_lib
+    wl = I.make_custom(kind=I.IID, m=4, s=12, t=5, w=I.w_logb(12, 5, 3), R=2, seed=5, b=3)
+    for r in range(wl.R):
+        X = brute.point_matrix(wl, r)
+        for j in range(wl.s):
+            vals = O.point_values(wl, r, j)
+            np.testing.assert_array_equal(vals[np.arange(wl.N) % len(vals)], X[:, j])
+        Yd = O.dense_matvec(O.point_matrix_unreduced(wl, r), wl.A.astype(np.float64))
+        assert np.linalg.norm(O.reduced_matvec(wl, r) - Yd) <= 1e-13 * np.linalg.norm(Yd)
+
+
+def test_base3_cos_mean_converges(oracle_lib):
+    """A randomly shifted base-3 lattice (m = 8, s = t = 64, 16 shifts): the
+    mean estimate lies within 4 standard errors of the closed-form integral."""
+    O = oracle_lib
+    s = t = 64
+    wl = I.make_custom(kind=I.LATTICE, m=8, s=s, t=t, w=I.w_logb(s, 6, 3), rand=I.RANDOM_SHIFT,
+                       R=16, seed=21, b=3, A_scale=1.0 / 8)
+    Q, _ = O.estimate(wl)
+    Iex = _cos_closed_form(wl.A.astype(np.float64))
+    se = Q.std(ddof=1) / math.sqrt(len(Q))
+    assert abs(Q.mean() - Iex) <= 4 * se
+    assert se < 1e-3
