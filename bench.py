@@ -212,7 +212,7 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--config", type=int, default=2, help="workload C1..C5 (default C2)")
+    ap.add_argument("--config", type=int, default=2, help="workload C1..C8 (default C2)")
     ap.add_argument("--prec", type=int, default=None, help="0 = FP32, 1 = split-BF16x3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dense", action="store_true")
@@ -275,11 +275,17 @@ def main() -> int:
     flops = 2.0 * wl.N * wl.s * wl.t * wl.R
     value = flops / (ms * 1e-3) / 1e9
     leaf_ms = kern.get("leaf", {}).get("avg_ms", float("nan"))
-    if pts.split_level < 0:
-        # Algorithm 4 (a net that is not periodic): the tile products run on the
-        # matrix cores, 2 N s t R flops per launch (three BF16 products each
-        # with the split precision)
-        mf = flops * (3 if prec == I.SPLIT_BF16X3 else 1)
+    if pts.split_level < 0 or wl.b != 2:
+        # gathered value tiles (a net that is not periodic, Algorithm 4; or a
+        # base b > 2): the tile products run on the matrix cores.  The timed
+        # kernel is the pass over all N points and the jlow lower coordinates
+        # (jlow = s in one pass; a base b > 2 with split level L' sums the
+        # coordinates with w_j >= L' over the b^{m-L'} residues first):
+        # 2 N jlow t R flops per launch (three BF16 products each with the
+        # split precision)
+        L = pts.split_level
+        jlow = wl.s if L < 0 else int(np.sum(np.minimum(wl.w, wl.m) < L))
+        mf = 2.0 * wl.N * jlow * wl.t * wl.R * (3 if prec == I.SPLIT_BF16X3 else 1)
         peak = MFMA_PEAK_TFLOPS[prec]
         achieved = mf / (leaf_ms * 1e-3) / 1e12
         roofline = {"bound": "mfma", "kernel": "alg4_kernel", "achieved": round(achieved, 3),

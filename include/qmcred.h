@@ -18,7 +18,9 @@
  *
  * Conventions for every call:
  *   - Indices are 0-based: coordinate j = 0..s-1 is the paper's j+1.
- *   - Only b = 2 is supported (QMC_EUNSUPPORTED otherwise), with 1 <= m <= 24.
+ *   - b is a prime.  Every kind is supported for b = 2 with 1 <= m <= 24;
+ *     lattices and reduced Monte Carlo also in a prime base b > 2 (without
+ *     the digital shift), with N = b^m <= 2^24 (QMC_EUNSUPPORTED otherwise).
  *   - Matrices are row-major FP32 with an explicit leading dimension.
  *   - "device" pointers are HIP device memory on the device that was current
  *     when the point set was created; "host" pointers are ordinary memory.
@@ -91,9 +93,9 @@ typedef enum { QMC_H_ID = 0, QMC_H_CALL = 1 /* max(0, u - K) */ } qmc_h;
  * host memory and are copied by qmc_points_init.
  *   w      [s]    reduction indices, w[0] = 0, non-decreasing, w[j] >= 0
  *                 (Section 1.3).  Coordinates with w[j] >= m take one value.
- *   gen    lattice: [s] z'_j with z'_j odd and < 2^{m-w_j}, or z'_j = 1 when
- *                 w_j >= m (the set U_{b^{m-w}} of Section 1.3); the
- *                 generating vector is z_j = b^{w_j} z'_j.
+ *   gen    lattice: [s] z'_j below b^{m-w_j} and not divisible by b (odd for
+ *                 b = 2), or z'_j = 1 when w_j >= m (the set U_{b^{m-w}} of
+ *                 Section 1.3); the generating vector is z_j = b^{w_j} z'_j.
  *          poly lattice: [s] bit masks of g'_j in F_2[x] (bit i = coefficient
  *                 of x^i), g'_j(0) = 1, deg g'_j < m - w_j (g'_j = 1 when
  *                 w_j >= m); the generating polynomial is x^{w_j} g'_j.
@@ -116,7 +118,7 @@ typedef enum { QMC_H_ID = 0, QMC_H_CALL = 1 /* max(0, u - K) */ } qmc_h;
  *   map           component map; QMC_MAP_INVNORM requires a shift because the
  *                 unshifted point x_0 = 0 (Section 2.3), or QMC_IID samples.
  *   samples       QMC_IID only: [R][sum_j n_j] uniforms in [0,1) (in (0,1)
- *                 with QMC_MAP_INVNORM), n_j = 2^{m - min(w_j, m)}; replicate
+ *                 with QMC_MAP_INVNORM), n_j = b^{m - min(w_j, m)}; replicate
  *                 r holds coordinate 0's n_0 samples, then coordinate 1's, ...
  *                 Copied to the device by qmc_points_init.
  */
@@ -149,8 +151,12 @@ typedef struct qmc_points_s *qmc_points;
  * decreasing, a generator outside its allowed set, shift outside [0,1) or
  * >= 2^52, R < 1, INVNORM without a shift, QMC_IID with a shift, without
  * samples or with a sample outside [0,1) ((0,1) under INVNORM);
- * EUNSUPPORTED: b != 2, m outside [1, 24]), plans the levels and uploads
- * generators, shifts and samples.
+ * EUNSUPPORTED: m outside [1, 24], b^m > 2^24, b > 2 with a digital net, a
+ * polynomial lattice or the digital shift), plans the levels and uploads
+ * generators, shifts and samples.  A base b > 2 is evaluated like Algorithm 4:
+ * the n_j values of every coordinate (Section 1.3: c / b^e, one correctly
+ * rounded FP64 division before shift and map; Section 4 for samples) are
+ * tabulated, and point k reads value k mod n_j.
  * Synchronous.  *out owns device memory; release with qmc_points_free.
  */
 qmc_status qmc_points_init(qmc_points *out, const qmc_point_spec *spec);
@@ -158,10 +164,10 @@ qmc_status qmc_points_init(qmc_points *out, const qmc_point_spec *spec);
 /* Release a point set.  NULL is accepted.  The caller ensures no call is in flight. */
 qmc_status qmc_points_free(qmc_points p);
 
-/* Host-side facts about a point set: N = 2^m, s, R, the split level used by
+/* Host-side facts about a point set: N = b^m, s, R, the split level used by
  * the fused kernels (-1 for a net that is not periodic after reduction, whose
- * products use Algorithm 4) and the number of distinct values sum_j n_j per
- * shift. */
+ * products use Algorithm 4, and for a base b > 2) and the number of distinct
+ * values sum_j n_j per shift. */
 qmc_status qmc_points_info(qmc_points p, int64_t *N, int32_t *s, int32_t *R, int32_t *split_level,
                            int64_t *distinct_values);
 
@@ -217,7 +223,8 @@ qmc_status qmc_estimate(qmc_points p, const float *A, int32_t t, int64_t lda, co
  * sensitivities over the residue classes k mod n_j, then the distinct values),
  * with Y recomputed rather than stored.  dA: device, R x s x t FP32, rows of
  * length t (leading dimension t).  workspace as above (op = 2).
- * QMC_EUNSUPPORTED for a net that is not periodic after reduction.
+ * QMC_EUNSUPPORTED for a net that is not periodic after reduction and for a
+ * base b > 2.
  */
 qmc_status qmc_estimate_grad(qmc_points p, const float *A, int32_t t, int64_t lda,
                              const qmc_integrand *f, int32_t prec, double *Q, float *dA,

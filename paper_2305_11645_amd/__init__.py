@@ -75,8 +75,8 @@ class Points:
         h = ct.c_void_p()
         check(L.qmc_points_init(ct.byref(h), ct.byref(spec)))
         self._h = h
-        self.m, self.s, self.R, self.kind, self.map, self.rand = m, s, R, kind, map, rand
-        self.N = 1 << m
+        self.b, self.m, self.s, self.R, self.kind, self.map, self.rand = b, m, s, R, kind, map, rand
+        self.N = b ** m
         N, s_, R_, sp, dv = ct.c_int64(), ct.c_int32(), ct.c_int32(), ct.c_int32(), ct.c_int64()
         check(L.qmc_points_info(h, ct.byref(N), ct.byref(s_), ct.byref(R_), ct.byref(sp), ct.byref(dv)))
         self.split_level = sp.value
@@ -86,7 +86,8 @@ class Points:
     @classmethod
     def from_workload(cls, wl) -> "Points":
         return cls(kind=wl.kind, m=wl.m, s=wl.s, w=wl.w, gen=wl.gen, rand=wl.rand, R=wl.R,
-                   shift=wl.shift, dshift=wl.dshift, map=wl.map, samples=getattr(wl, "samples", None))
+                   shift=wl.shift, dshift=wl.dshift, map=wl.map, samples=getattr(wl, "samples", None),
+                   b=wl.b)
 
     @property
     def handle(self) -> ct.c_void_p:
@@ -129,7 +130,7 @@ def point_values(pts: Points, r: int, j: int):
     """FP64 distinct values of coordinate j for randomisation r (device tensor)."""
     torch = _torch()
     nb = pts.m - min(int(pts._w[j]), pts.m)
-    out = torch.empty(1 << nb, dtype=torch.float64, device=f"cuda:{pts.device}")
+    out = torch.empty(pts.b ** nb, dtype=torch.float64, device=f"cuda:{pts.device}")
     check(load().qmc_point_values(pts.handle, r, j, ct.c_void_p(out.data_ptr()), _stream()))
     return out
 

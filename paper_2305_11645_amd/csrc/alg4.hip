@@ -1,4 +1,6 @@
-// Reduced digital nets that are not periodic (Section 3, Algorithm 4).
+// Products by gathered value tiles on the matrix cores: reduced digital nets
+// that are not periodic (Section 3, Algorithm 4), and reduced point sets in a
+// prime base b > 2 (Section 1.3, Section 4), whose index is n mod n_j.
 //
 // After the row reduction of eq. reduced_genmat_net2, coordinate j of such a
 // net still depends on every digit of the point index n, but takes only the
@@ -46,8 +48,12 @@ constexpr int XPAD = TK + 1;               // X tile row stride (odd: conflict-f
 
 struct Alg4Args {
   int32_t m, s, t, tct;
-  int64_t N, lda, ldy, tab_stride;
+  int32_t j0, sc;        // the pass sums coordinates [j0, j0 + sc)
+  int64_t N, lda, ldy, tab_stride;  // N: points of the pass
   int64_t ntiles;        // ceil(N / 64)
+  int64_t ystride;       // StoreY: floats between the randomisations' outputs
+  const float *root;     // optional root table added to y: row n mod nsplit
+  int64_t ldp, root_stride, nsplit;
   float sigma;           // y' = sigma y (scale of g)
 };
 
@@ -61,8 +67,12 @@ __device__ __forceinline__ float load_f32(__amdgpu_buffer_rsrc_t r, uint32_t byt
   return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)byte_off, 0, 0));
 }
 
-template <int PREC, int MODE, int GF>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC == QMC_FP32 ? 3 : 2))) void alg4_kernel(Alg4Args a, DevSpec D, const float *__restrict__ tab,
+// IDX: how a point's value index combines the tile word and the lane word
+// (0: XOR, nets that are not periodic; 1: add, base b > 2).
+// (FP32 nets run at three waves per SIMD; the root-table epilogue of the add
+// index needs the registers of two.)
+template <int PREC, int MODE, int GF, int IDX>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC == QMC_FP32 && !IDX ? 3 : 2))) void alg4_kernel(Alg4Args a, DevSpec D, const float *__restrict__ tab,
                                                    const float *__restrict__ A, float *__restrict__ Y,
                                                    double *__restrict__ partial,
                                                    float *__restrict__ ppart) {
@@ -76,7 +86,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC == QMC
   const int wc = w * 64;
   const int64_t n0 = (int64_t)tn * TM;
   const __amdgpu_buffer_rsrc_t trs = raw_rsrc(tab + (int64_t)rl * a.tab_stride, (uint32_t)(a.tab_stride * 4));
-  const uint32_t *ytile = D.ytile + (int64_t)tn * a.s;  // aoff_j XOR y_j(n0) for every j
+  const uint32_t *ytile = D.ytile + (int64_t)tn * a.s;  // the tile words of every coordinate
 
   // Only wave w reads columns [wc, wc + 64) of the tile, so its B operands come
   // straight from A into registers, one step ahead.  Element e < TK of a lane:
@@ -92,24 +102,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC == QMC
   for (int c = 0; c < 2; ++c)
     boff[c] = (uint32_t)(((int64_t)bh * a.lda + min(ct * TN + wc + 32 * c + (lane & 31), a.t - 1)) * 4);
 
-  // Step k0: wave w gathers coordinates k0 + KPW w + q (q < KPW) of the 64
-  // points (lane = point); a value's byte offset is 4 (ytile_j XOR ylo_j(lane)).
-  // Coordinates past s gather coordinate s - 1 (its rows of A read zero), points
-  // past N gather valid values (their outputs are dropped).
+  // Step k0: wave w gathers coordinates j0 + k0 + KPW w + q (q < KPW) of the 64
+  // points (lane = point); a value's byte offset is 4 (ytile_j op ylo_j(lane)).
+  // Coordinates past the pass's last gather that one (its rows of A read zero),
+  // points past N gather valid values (their outputs are dropped).
   uint32_t yl[KPW], yt[KPW];  // index words of the next coordinates to gather
   float xv[KPW];
   auto load_index = [&](int k0) {
 #pragma unroll
     for (int q = 0; q < KPW; ++q) {
-      const int j = min(k0 + KPW * w + q, a.s - 1);
+      const int j = a.j0 + min(k0 + KPW * w + q, a.sc - 1);
       yl[q] = D.ylo[(int64_t)j * 64 + lane];
       yt[q] = ytile[j];
     }
   };
   auto load_values = [&](int k0, float (&b)[TK]) {
 #pragma unroll
-    for (int q = 0; q < KPW; ++q) xv[q] = load_f32(trs, (yt[q] ^ yl[q]) << 2);
-    const int64_t left = (int64_t)a.s - k0;  // rows of A from row k0 on
+    for (int q = 0; q < KPW; ++q) xv[q] = load_f32(trs, (IDX ? yt[q] + yl[q] : yt[q] ^ yl[q]) << 2);
+    const int64_t left = (int64_t)a.sc - k0;  // rows of A from row k0 on
     const int64_t want = ((left - 1) * a.lda + a.t) * 4;
     const uint32_t bytes = left <= 0 ? 0u : want > 0xffffffffll ? 0xffffffffu : (uint32_t)want;
     const __amdgpu_buffer_rsrc_t ars = raw_rsrc(left <= 0 ? A : A + (int64_t)k0 * a.lda, bytes);
@@ -191,8 +201,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC == QMC
   load_index(TK);
   store_x(Xs[0]);
   __syncthreads();
-  // steps past s multiply zero rows of A
-  for (int k0 = 0; k0 < a.s; k0 += 2 * TK) {
+  // steps past the pass's coordinates multiply zero rows of A
+  for (int k0 = 0; k0 < a.sc; k0 += 2 * TK) {
     step(k0, b0, b1, Xs[0], Xs[1]);
     step(k0 + TK, b1, b0, Xs[1], Xs[0]);
   }
@@ -201,7 +211,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC == QMC
   // wc + 32 c + lane % 32) of the tile
   auto row_of = [&](int i, int v) { return 32 * i + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3); };
   const int colw = ct * TN + wc + (lane & 31);
+  if (IDX && a.root) {  // the upper levels' sum, P[n mod nsplit] (nsplit >= 64; base b > 2 only)
+    const float *rt = a.root + (int64_t)rl * a.root_stride;
+    const int64_t base = n0 % a.nsplit;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        int64_t p = base + row_of(i, v);
+        if (p >= a.nsplit) p -= a.nsplit;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) acc[i][c][v] += rt[p * a.ldp + min(colw + 32 * c, a.t - 1)];
+      }
+  }
   if (MODE == kModeStoreY) {
+    Y += (int64_t)rl * a.ystride;
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -258,11 +282,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC == QMC
         ((rsum[0][tid] + rsum[1][tid]) + rsum[2][tid]) + rsum[3][tid];
 }
 
-template <int PREC, int MODE>
+template <int PREC, int MODE, int IDX>
 static void launch_g(int gf, dim3 grid, hipStream_t st, const Alg4Args &a, const DevSpec &D,
                      const float *tab, const float *A, const Alg4Out &o) {
-#define QMC_ALG4(GF)                                                                               \
-  hipLaunchKernelGGL((alg4_kernel<PREC, MODE, GF>), grid, dim3(256), 0, st, a, D, tab, A, o.Y, \
+#define QMC_ALG4(GF)                                                                                    \
+  hipLaunchKernelGGL((alg4_kernel<PREC, MODE, GF, IDX>), grid, dim3(256), 0, st, a, D, tab, A, o.Y, \
                      o.partial, o.ppart)
   if (gf == QMC_G_COS) QMC_ALG4(QMC_G_COS);
   else if (gf == QMC_G_EXP) QMC_ALG4(QMC_G_EXP);
@@ -270,21 +294,23 @@ static void launch_g(int gf, dim3 grid, hipStream_t st, const Alg4Args &a, const
 #undef QMC_ALG4
 }
 
-template <int PREC>
+template <int PREC, int IDX>
 static void launch_m(int mode, int gf, dim3 grid, hipStream_t st, const Alg4Args &a,
                      const DevSpec &D, const float *tab, const float *A, const Alg4Out &o) {
-  if (mode == kModeStoreY) launch_g<PREC, kModeStoreY>(QMC_G_ID, grid, st, a, D, tab, A, o);
-  else if (mode == kModeSum) launch_g<PREC, kModeSum>(gf, grid, st, a, D, tab, A, o);
-  else launch_g<PREC, kModePoint>(gf, grid, st, a, D, tab, A, o);
+  if (mode == kModeStoreY) launch_g<PREC, kModeStoreY, IDX>(QMC_G_ID, grid, st, a, D, tab, A, o);
+  else if (mode == kModeSum) launch_g<PREC, kModeSum, IDX>(gf, grid, st, a, D, tab, A, o);
+  else launch_g<PREC, kModePoint, IDX>(gf, grid, st, a, D, tab, A, o);
 }
 
 }  // namespace
 
+// Index words of the gather path (layout at DevSpec::aoff).  Nets (add = 0):
 // ylo[j][r] = y_j(r) for r < 64 (rows past N: digits that do not exist are
-// dropped) and ytile[h][j] = aoff_j XOR y_j(64 h) for h < ceil(N / 64), each
-// word restricted to its first n_j digits.  aoff_j, the start of coordinate j's
-// table, is a multiple of n_j, so aoff_j XOR y = aoff_j + y for y < n_j.
-__global__ __launch_bounds__(256) void alg4_index_kernel(int32_t m, int32_t s, int64_t ntiles,
+// dropped) and ytile[h][j] = aoff_j XOR y_j(64 h), each word restricted to its
+// first n_j digits; aoff_j is a multiple of n_j, so aoff_j XOR y = aoff_j + y
+// for y < n_j.  Base b > 2 (add = 1): ylo[j][r] = r mod n_j and ytile[h][j] =
+// aoff_j + (64 h mod n_j), whose sum stays below aoff_j + 2 n_j.
+__global__ __launch_bounds__(256) void alg4_index_kernel(int32_t m, int32_t s, int32_t b, int64_t ntiles,
                                                          const uint32_t *__restrict__ gen,
                                                          const int32_t *__restrict__ nbj,
                                                          const uint32_t *__restrict__ aoff,
@@ -293,19 +319,26 @@ __global__ __launch_bounds__(256) void alg4_index_kernel(int32_t m, int32_t s, i
   const int64_t nlo = (int64_t)64 * s, total = nlo + ntiles * s;
   const uint32_t lowmask = m >= 6 ? 63u : ((1u << m) - 1u);
   for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+    const bool lo = e < nlo;
+    const int64_t h = lo ? 0 : (e - nlo) / s;
+    const int64_t j = lo ? e >> 6 : (e - nlo) - h * s;
+    const int nb = nbj[j];
+    if (b != 2) {
+      uint64_t n = 1;
+      for (int i = 0; i < nb; ++i) n *= (uint32_t)b;
+      if (lo) ylo[e] = (uint32_t)((uint64_t)(e & 63) % n);
+      else ytile[e - nlo] = aoff[j] + (uint32_t)((uint64_t)(64 * h) % n);
+      continue;
+    }
+    const uint32_t *col = gen + j * m;
+    const uint32_t msk = nb >= 32 ? 0xffffffffu : (1u << nb) - 1u;
     uint32_t y = 0;
-    if (e < nlo) {
-      const int64_t j = e >> 6;
-      const uint32_t *col = gen + j * m;
-      for (uint32_t b = (uint32_t)(e & 63) & lowmask; b; b &= b - 1u) y ^= col[__builtin_ctz(b)];
-      const int nb = nbj[j];
-      ylo[e] = nb >= 32 ? y : y & ((1u << nb) - 1u);
+    if (lo) {
+      for (uint32_t bits = (uint32_t)(e & 63) & lowmask; bits; bits &= bits - 1u) y ^= col[__builtin_ctz(bits)];
+      ylo[e] = y & msk;
     } else {
-      const int64_t h = (e - nlo) / s, j = (e - nlo) - h * s;
-      const uint32_t *col = gen + j * m;
-      for (uint32_t b = (uint32_t)h; b; b &= b - 1u) y ^= col[6 + __builtin_ctz(b)];
-      const int nb = nbj[j];
-      ytile[e - nlo] = aoff[j] ^ (nb >= 32 ? y : y & ((1u << nb) - 1u));
+      for (uint32_t bits = (uint32_t)h; bits; bits &= bits - 1u) y ^= col[6 + __builtin_ctz(bits)];
+      ytile[e - nlo] = aoff[j] ^ (y & msk);
     }
   }
 }
@@ -320,32 +353,58 @@ hipError_t launch_alg4_index(const Geometry &G, const uint32_t *gen, const int32
                              uint32_t *ylo, uint32_t *ytile, hipStream_t st) {
   const int64_t total = alg4_index_words(G);
   const int64_t blocks = std::min<int64_t>(ceil_div(total, 256), 65535);
-  hipLaunchKernelGGL(alg4_index_kernel, dim3((unsigned)blocks), dim3(256), 0, st, G.m, G.s,
+  hipLaunchKernelGGL(alg4_index_kernel, dim3((unsigned)blocks), dim3(256), 0, st, G.m, G.s, G.b,
                      alg4_point_tiles(G), gen, nbj, aoff, ylo, ytile);
   return hipGetLastError();
 }
 
+Alg4Pass alg4_whole(const Geometry &G) {
+  Alg4Pass ps{};
+  ps.j0 = 0;
+  ps.sc = G.s;
+  ps.npts = G.N;
+  ps.timer = "leaf";
+  return ps;
+}
+
 hipError_t launch_alg4(const Geometry &G, const DevSpec &D, int mode, const qmc_integrand &f,
                        int prec, const float *tab, int nr, const float *A, int t, int64_t lda,
-                       const Alg4Out &o, hipStream_t st) {
-  LaunchTimer tm("leaf", st);
+                       const Alg4Pass &ps, const Alg4Out &o, hipStream_t st) {
+  LaunchTimer tm(ps.timer, st);
   if (mode != kModeStoreY && mode != kModeSum && mode != kModePoint) return hipErrorInvalidValue;
   // byte offsets of a step's rows of A and of the value tables are 32-bit
-  if (lda > kAlg4MaxLda || D.sample_total * 4 > 0xffffffffll) return hipErrorInvalidValue;
+  if (lda > kAlg4MaxLda || G.gather_total * 4 > 0xffffffffll) return hipErrorInvalidValue;
+  if (ps.sc < 1 || ps.j0 < 0 || ps.j0 + ps.sc > G.s || ps.npts < 1 || ps.npts > G.N ||
+      (ps.root && ps.nsplit < TM))
+    return hipErrorInvalidValue;
   Alg4Args a{};
   a.m = G.m;
   a.s = G.s;
   a.t = t;
   a.tct = alg4_col_tiles(t);
-  a.N = G.N;
+  a.j0 = ps.j0;
+  a.sc = ps.sc;
+  a.N = ps.npts;
   a.lda = lda;
   a.ldy = o.ldy;
-  a.tab_stride = D.sample_total;
-  a.ntiles = alg4_point_tiles(G);
+  a.ystride = o.ystride;
+  a.tab_stride = G.gather_total;
+  a.ntiles = ceil_div(ps.npts, TM);
+  a.root = ps.root;
+  a.ldp = ps.ldp;
+  a.root_stride = ps.root_stride;
+  a.nsplit = ps.nsplit;
   a.sigma = g_scale(f, mode);
+  A += (int64_t)ps.j0 * lda;
   const dim3 grid((unsigned)a.ntiles, a.tct, nr);
-  if (prec == QMC_FP32) launch_m<QMC_FP32>(mode, f.g, grid, st, a, D, tab, A, o);
-  else launch_m<QMC_SPLIT_BF16X3>(mode, f.g, grid, st, a, D, tab, A, o);
+  const bool add = G.b != 2;
+  if (prec == QMC_FP32) {
+    if (add) launch_m<QMC_FP32, 1>(mode, f.g, grid, st, a, D, tab, A, o);
+    else launch_m<QMC_FP32, 0>(mode, f.g, grid, st, a, D, tab, A, o);
+  } else {
+    if (add) launch_m<QMC_SPLIT_BF16X3, 1>(mode, f.g, grid, st, a, D, tab, A, o);
+    else launch_m<QMC_SPLIT_BF16X3, 0>(mode, f.g, grid, st, a, D, tab, A, o);
+  }
   return hipGetLastError();
 }
 

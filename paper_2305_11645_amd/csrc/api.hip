@@ -125,6 +125,40 @@ void plan_geometry(qmc::Geometry &G, const int32_t *w) {
   G.urows = uoff;
 }
 
+// Base b > 2: the gather path in two passes.  With n_split = b^{m - L'}, the
+// coordinates with min(w_j, m) >= L' (n_j <= n_split) are summed over the
+// n_split residues into a root table (the upper levels of Algorithm 2's
+// cascade), the jlow lower ones over all N points, which add the root row
+// n mod n_split.  L' (with n_split >= 64) minimises the matrix-core work in
+// whole 32-coordinate steps, N ceil32(jlow) + n_split ceil32(s - jlow), plus
+// the root rows read by every point, priced as 16 multiply-adds per column;
+// one pass (jlow = s) when that is cheaper.
+void plan_gather_split(qmc::Geometry &G, const int32_t *w, int64_t Nb) {
+  G.N = Nb;
+  G.split = -1;
+  G.jlow = G.s;
+  G.nsub = 0;
+  auto steps = [](int64_t k) { return (k + 31) / 32 * 32; };
+  int64_t best = Nb * steps(G.s);
+  int64_t nsplit = Nb;
+  int force = -2;  // QMC_SPLIT_LEVEL: a level to take instead of the cheapest (-1: one pass)
+  if (const char *env = getenv("QMC_SPLIT_LEVEL")) force = atoi(env);
+  for (int L = 1; L <= G.m; ++L) {
+    nsplit /= G.b;
+    if (nsplit < 64) break;
+    int jl = 0;
+    while (jl < G.s && (w[jl] < G.m ? w[jl] : G.m) < L) ++jl;
+    const int64_t cost = force == L ? 0 : force >= -1 ? best
+                                                      : Nb * steps(jl) + nsplit * steps(G.s - jl) + 16 * Nb;
+    if (cost < best) {
+      best = cost;
+      G.split = L;
+      G.jlow = jl;
+      G.nsub = nsplit;
+    }
+  }
+}
+
 // ------------------------------------------------------------ workspace
 struct Carve {
   char *base;
@@ -140,7 +174,7 @@ struct Carve {
 enum Op { kOpMatvec = 0, kOpEstimate = 1, kOpGrad = 2 };
 
 struct Work {
-  float *tables, *U, *ppart, *S, *dlow, *dup, *hd;
+  float *tables, *U, *ppart, *S, *dlow, *dup, *hd, *root;
   double *partial, *ppartial;
 };
 
@@ -153,10 +187,9 @@ size_t carve(const qmc::Geometry &G, int op, int t, const qmc_integrand *f, int 
   const LeafPlan lp = leaf_plan(G, t, nr, kModeSum, f->g);
   const LeafPlan lg = leaf_plan(G, t, nr, kModeGrad, f->g);
   wk = Work{};
-  if (G.nonperiodic) {  // Algorithm 4: value tables, partials of the 64 x 64 tiles
-    int64_t total = 0;
-    for (int I = 0; I <= G.m; ++I) total += (int64_t)G.lev[I].tau << G.lev[I].nb;
-    wk.tables = c.take<float>((size_t)nr * total);
+  if (G.gather) {  // value tables, root table, partials of the 64-point x 256-column tiles
+    wk.tables = c.take<float>((size_t)nr * G.gather_total);
+    if (G.jlow < G.s) wk.root = c.take<float>((size_t)nr * G.nsub * t);
     if (op == kOpMatvec) return c.used;
     const int64_t atct = alg4_col_tiles(t);
     wk.partial = c.take<double>((size_t)nr * alg4_point_tiles(G) * atct);
@@ -311,10 +344,15 @@ qmc_status qmc_points_init(qmc_points *out, const qmc_point_spec *sp) {
   *out = nullptr;
   if (!sp) return fail(QMC_EINVAL, "spec is null");
   if (!is_prime(sp->b)) return fail(QMC_EINVAL, "b = %d is not prime", sp->b);
-  if (sp->b != 2) return fail(QMC_EUNSUPPORTED, "only b = 2 is supported (b = %d)", sp->b);
+  const int b = sp->b;
   if (sp->m < 1 || sp->m > kMaxM) return fail(QMC_EUNSUPPORTED, "m = %d outside [1, %d]", sp->m, kMaxM);
+  int64_t Nb = 1;  // N = b^m
+  for (int i = 0; i < sp->m && Nb <= kMaxPoints; ++i) Nb *= b;
+  if (Nb > kMaxPoints) return fail(QMC_EUNSUPPORTED, "N = %d^%d exceeds %lld points", b, sp->m, (long long)kMaxPoints);
   if (sp->s < 1) return fail(QMC_EINVAL, "s = %d must be >= 1", sp->s);
   if (sp->kind < QMC_LATTICE || sp->kind > QMC_IID) return fail(QMC_EINVAL, "unknown kind %d", sp->kind);
+  if (b != 2 && sp->kind != QMC_LATTICE && sp->kind != QMC_IID)
+    return fail(QMC_EUNSUPPORTED, "digital nets and polynomial lattices are built for b = 2 only (b = %d)", b);
   const bool iid = sp->kind == QMC_IID;
   if (!sp->w || (!sp->gen && !iid)) return fail(QMC_EINVAL, "w or gen is null");
   const int m = sp->m, s = sp->s;
@@ -345,16 +383,21 @@ qmc_status qmc_points_init(qmc_points *out, const qmc_point_spec *sp) {
     gen.resize(s);
     for (int j = 0; j < s; ++j) {
       const uint64_t z = sp->gen[j];
+      uint64_t nj = 1;
+      for (int i = 0; i < nbv[j]; ++i) nj *= (uint64_t)b;
       if (nbv[j] == 0) {
         if (z != 1) return fail(QMC_EINVAL, "generator of coordinate %d must be 1 (w_j >= m)", j);
-      } else if ((z & 1u) == 0 || z >= (uint64_t(1) << nbv[j])) {
-        return fail(QMC_EINVAL, "generator %llu of coordinate %d is not a unit below 2^%d",
-                    (unsigned long long)z, j, nbv[j]);
+      } else if (z % (uint64_t)b == 0 || z >= nj) {
+        // a unit modulo b^e: below b^e and not divisible by the prime b
+        return fail(QMC_EINVAL, "generator %llu of coordinate %d is not a unit below %d^%d",
+                    (unsigned long long)z, j, b, nbv[j]);
       }
       gen[j] = (uint32_t)z;
     }
   }
   if (sp->rand < QMC_NO_SHIFT || sp->rand > QMC_DIGITAL_SHIFT) return fail(QMC_EINVAL, "unknown randomisation %d", sp->rand);
+  if (b != 2 && sp->rand == QMC_DIGITAL_SHIFT)
+    return fail(QMC_EUNSUPPORTED, "the digital shift is built for b = 2 only (b = %d)", b);
   if (sp->R < 1) return fail(QMC_EINVAL, "R = %d must be >= 1", sp->R);
   if (iid && sp->rand != QMC_NO_SHIFT)
     return fail(QMC_EINVAL, "reduced Monte Carlo takes no shift (R counts independent replicates)");
@@ -377,7 +420,9 @@ qmc_status qmc_points_init(qmc_points *out, const qmc_point_spec *sp) {
   int64_t sample_total = 0;
   for (int j = 0; j < s; ++j) {
     soff[j] = sample_total;
-    sample_total += int64_t(1) << nbv[j];
+    int64_t nj = 1;
+    for (int i = 0; i < nbv[j]; ++i) nj *= b;
+    sample_total += nj;
   }
   if (iid) {
     if (!sp->samples) return fail(QMC_EINVAL, "samples is null");
@@ -401,8 +446,17 @@ qmc_status qmc_points_init(qmc_points *out, const qmc_point_spec *sp) {
   G.rand = sp->rand;
   G.map = sp->map;
   G.R = sp->R;
+  G.b = b;
   G.nonperiodic = nonperiodic ? 1 : 0;
   plan_geometry(G, sp->w);
+  // the cascade below is planned in base 2; a base b > 2 takes the gather path
+  G.gather = nonperiodic || b != 2 ? 1 : 0;
+  if (nonperiodic) G.jlow = s;  // one pass over every coordinate
+  if (b != 2) plan_gather_split(G, sp->w, Nb);
+  G.gather_total = nonperiodic ? sample_total : b != 2 ? 2 * sample_total : 0;
+  if (G.gather_total > kAlg4MaxValues)
+    return fail(QMC_EUNSUPPORTED, "value tables of %lld floats exceed %lld", (long long)G.gather_total,
+                (long long)kAlg4MaxValues);
 
   auto cleanup = [&](qmc_status st) {
     qmc_points_free(p);
@@ -437,20 +491,22 @@ qmc_status qmc_points_init(qmc_points *out, const qmc_point_spec *sp) {
   if ((e = hipMalloc(&p->d_soff, (size_t)s * 8)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc"));
   if ((e = hipMemcpy(p->d_soff, soff.data(), (size_t)s * 8, hipMemcpyHostToDevice)) != hipSuccess)
     return cleanup(hip_fail(e, "hipMemcpy"));
-  if (nonperiodic) {  // Algorithm 4: table starts and index words, once
-    // tables in order of decreasing n_j: every start is a multiple of its n_j
-    std::vector<int> ord(s);
-    for (int j = 0; j < s; ++j) ord[j] = j;
-    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return nbv[x] > nbv[y]; });
+  if (G.gather) {  // gather path: table starts and index words, once
     std::vector<uint32_t> aoff(s);
-    int64_t pos = 0;
-    for (int j : ord) {
-      aoff[j] = (uint32_t)pos;
-      pos += int64_t(1) << nbv[j];
+    if (nonperiodic) {
+      // tables in order of decreasing n_j: every start is a multiple of its n_j
+      std::vector<int> ord(s);
+      for (int j = 0; j < s; ++j) ord[j] = j;
+      std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return nbv[x] > nbv[y]; });
+      int64_t pos = 0;
+      for (int j : ord) {
+        aoff[j] = (uint32_t)pos;
+        pos += int64_t(1) << nbv[j];
+      }
+    } else {
+      // base b > 2: each table holds its n_j values twice
+      for (int j = 0; j < s; ++j) aoff[j] = (uint32_t)(2 * soff[j]);
     }
-    if (pos > kAlg4MaxValues)
-      return cleanup(fail(QMC_EUNSUPPORTED, "Algorithm 4 value tables of %lld values exceed %lld",
-                          (long long)pos, (long long)kAlg4MaxValues));
     const size_t words = (size_t)alg4_index_words(G);
     if ((e = hipMalloc(&p->d_yidx, (words + s) * 4)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc"));
     uint32_t *ylo = static_cast<uint32_t *>(p->d_yidx), *ytile = ylo + (size_t)64 * s, *daoff = ylo + words;
@@ -495,8 +551,9 @@ qmc_status qmc_points_info(qmc_points p, int64_t *N, int32_t *s, int32_t *R, int
   if (N) *N = p->G.N;
   if (s) *s = p->G.s;
   if (R) *R = p->G.R;
-  if (split_level) *split_level = p->G.nonperiodic ? -1 : p->G.split;  // -1: Algorithm 4, no cascade
-  if (distinct_values) *distinct_values = p->G.nonperiodic ? p->D.sample_total : p->G.table_total;
+  // -1: gathered tiles in one pass; base b > 2 with a root table reports its level
+  if (split_level) *split_level = p->G.gather && p->G.jlow == p->G.s ? -1 : p->G.split;
+  if (distinct_values) *distinct_values = p->G.gather ? p->D.sample_total : p->G.table_total;
   return QMC_OK;
 }
 
@@ -539,6 +596,37 @@ qmc_status qmc_workspace_size(qmc_points p, int32_t op, int32_t t, const qmc_int
   return QMC_OK;
 }
 
+// Gather path: for a base b > 2 with a split, the upper coordinates over the
+// n_split residues into the root table (timed as "levels"), then the lower
+// coordinates over all N points adding the root rows; otherwise one pass.
+static hipError_t gather_passes(const qmc::Geometry &G, const qmc::DevSpec &D, int mode,
+                                const qmc_integrand &f, int prec, const float *tables, int nr,
+                                const float *A, int t, int64_t lda, float *root, const qmc::Alg4Out &o,
+                                hipStream_t st) {
+  using namespace qmc;
+  Alg4Pass lower = alg4_whole(G);
+  if (G.jlow < G.s) {
+    Alg4Pass up{};
+    up.j0 = G.jlow;
+    up.sc = G.s - G.jlow;
+    up.npts = G.nsub;
+    up.timer = "levels";
+    Alg4Out ro{};
+    ro.Y = root;
+    ro.ldy = t;
+    ro.ystride = G.nsub * t;
+    const qmc_integrand fid{QMC_G_ID, 0.0, QMC_H_ID, 0.0};
+    const hipError_t e = launch_alg4(G, D, kModeStoreY, fid, prec, tables, nr, A, t, lda, up, ro, st);
+    if (e != hipSuccess) return e;
+    lower.sc = G.jlow;
+    lower.root = root;
+    lower.ldp = t;
+    lower.root_stride = G.nsub * t;
+    lower.nsplit = G.nsub;
+  }
+  return launch_alg4(G, D, mode, f, prec, tables, nr, A, t, lda, lower, o, st);
+}
+
 qmc_status qmc_reduced_matvec(qmc_points p, int32_t r, const float *A, int32_t t, int64_t lda,
                               int32_t prec, float *Y, int64_t ldy, void *workspace,
                               size_t workspace_bytes, void *stream) {
@@ -559,12 +647,13 @@ qmc_status qmc_reduced_matvec(qmc_points p, int32_t r, const float *A, int32_t t
   carve(p->G, kOpMatvec, t, &fid, 1, base, wk);
   const int64_t ldu = round_up(t, kTileT);
   const Geometry &G = p->G;
-  if (G.nonperiodic) {  // Algorithm 4
+  if (G.gather) {  // gathered value tiles
     QMC_HIP(launch_output_tables(G, p->D, r, 1, wk.tables, st), "tables launch");
     Alg4Out o{};
     o.Y = Y;
     o.ldy = ldy;
-    QMC_HIP(launch_alg4(G, p->D, kModeStoreY, fid, prec, wk.tables, 1, A, t, lda, o, st), "Algorithm 4 launch");
+    QMC_HIP(gather_passes(G, p->D, kModeStoreY, fid, prec, wk.tables, 1, A, t, lda, wk.root, o, st),
+            "gathered tiles launch");
     return QMC_OK;
   }
   QMC_HIP(launch_tables(G, p->D, r, 1, wk.tables, nullptr, 0, st), "tables launch");
@@ -591,8 +680,10 @@ static qmc_status estimate_impl(qmc_points p, const float *A, int32_t t, int64_t
   const Geometry &G = p->G;
   const int nr = G.R;
   const int op = grad ? kOpGrad : kOpEstimate;
-  if (grad && G.nonperiodic)
-    return fail(QMC_EUNSUPPORTED, "the gradient of a net that is not periodic after reduction (Algorithm 4) is not provided");
+  if (grad && G.gather)
+    return fail(QMC_EUNSUPPORTED, G.nonperiodic
+                    ? "the gradient of a net that is not periodic after reduction (Algorithm 4) is not provided"
+                    : "the gradient in a base b > 2 is not provided");
   Work wk;
   const size_t need = carve(G, op, t, f, nr, nullptr, wk);
   CallWorkspace own;
@@ -606,17 +697,19 @@ static qmc_status estimate_impl(qmc_points p, const float *A, int32_t t, int64_t
   const bool sep = f->h == QMC_H_ID;
   const double inv_nt = 1.0 / ((double)G.N * (double)t);
 
-  if (G.nonperiodic) {  // Algorithm 4: value tables, then the fused tile products
+  if (G.gather) {  // value tables, then the fused tile products
     QMC_HIP(launch_output_tables(G, p->D, 0, nr, wk.tables, st), "tables launch");
     Alg4Out o{};
     if (sep) {
       o.partial = wk.partial;
-      QMC_HIP(launch_alg4(G, p->D, kModeSum, *f, prec, wk.tables, nr, A, t, lda, o, st), "Algorithm 4 launch");
+      QMC_HIP(gather_passes(G, p->D, kModeSum, *f, prec, wk.tables, nr, A, t, lda, wk.root, o, st),
+              "gathered tiles launch");
       QMC_HIP(launch_reduce(wk.partial, nr, alg4_point_tiles(G) * alg4_col_tiles(t), inv_nt, Q, st),
               "reduce launch");
     } else {
       o.ppart = wk.ppart;
-      QMC_HIP(launch_alg4(G, p->D, kModePoint, *f, prec, wk.tables, nr, A, t, lda, o, st), "Algorithm 4 launch");
+      QMC_HIP(gather_passes(G, p->D, kModePoint, *f, prec, wk.tables, nr, A, t, lda, wk.root, o, st),
+              "gathered tiles launch");
       const int64_t blocks = point_h_blocks(G);
       QMC_HIP(launch_point_h(G, *f, wk.ppart, nr, alg4_col_tiles(t), t, wk.ppartial, blocks, nullptr, 1.0, st),
               "point h launch");

@@ -28,6 +28,7 @@
 namespace qmc {
 
 constexpr int kMaxM = 24;
+constexpr int64_t kMaxPoints = int64_t(1) << 24;  // N = b^m
 constexpr int kMaxLevels = kMaxM + 1;
 constexpr int kMaxSplit = 6;       // at most 64 leaves per subtree
 constexpr int kTileT = 64;         // columns per wave in the leaf kernels
@@ -47,7 +48,11 @@ struct Level {
 // Everything a kernel needs to know about the point set (passed by value).
 struct Geometry {
   int32_t m, s, kind, rand, map, R;
+  int32_t b;             // prime base: N = b^m, n_j = b^{m - min(w_j, m)}
   int32_t nonperiodic;   // a reduced net that is not periodic: products by Algorithm 4
+  int32_t gather;        // products by gathered value tiles on the matrix cores: nets that
+                         // are not periodic (index by XOR) and every base b > 2 (index by add)
+  int64_t gather_total;  // floats per randomisation in the value tables of the gather path
   int32_t split;         // L'
   int32_t jlow;          // rows 0..jlow-1 of A belong to the lower levels
   int32_t nup;           // number of upper levels with tau > 0
@@ -70,10 +75,14 @@ struct DevSpec {
   const double *samples;   // reduced Monte Carlo: [R][sample_total]
   const int64_t *soff;     // [s] start of coordinate j's samples in a replicate
   int64_t sample_total;    // sum_j n_j
-  // Algorithm 4 (nets that are not periodic): aoff[j] = start of coordinate j's
-  // value table, a multiple of n_j; index words restricted to the first n_j
-  // digits, ylo[j * 64 + r] = y_j(r) for r < 64, ytile[h * s + j] =
-  // aoff[j] XOR y_j(64 h)
+  // Gather path: aoff[j] = start of coordinate j's value table; point n0 + r of
+  // tile h (n0 = 64 h, r < 64) reads the value at ytile[h * s + j] op
+  // ylo[j * 64 + r].
+  //   nets that are not periodic (op XOR): the words are the digit words y_j
+  //   restricted to the first n_j digits, ylo = y_j(r), ytile = aoff[j] XOR
+  //   y_j(64 h), and aoff[j] is a multiple of n_j;
+  //   base b > 2 (op +): the table holds the n_j values twice (2 n_j floats),
+  //   ylo = r mod n_j, ytile = aoff[j] + (64 h mod n_j).
   const uint32_t *aoff;
   const uint32_t *ylo;
   const uint32_t *ytile;
@@ -127,10 +136,12 @@ hipError_t launch_tables(const Geometry &G, const DevSpec &D, int r0, int nr, fl
 hipError_t launch_point_values(const Geometry &G, const DevSpec &D, int r, int j, double *out,
                                hipStream_t st);
 // Dense FP32 point matrix for shift r.
-// Algorithm 4 value tables in digit order: T_j[y] = X_j[c] for y < n_j, c the
-// integer of the reduced output digits and y its n_j-digit bit reversal (the
-// digits as the generating matrix produces them); sum_j n_j floats per
-// randomisation, coordinate j's block at DevSpec::aoff[j].
+// Value tables of the gather path, coordinate j's block at DevSpec::aoff[j],
+// Geometry::gather_total floats per randomisation.  Nets that are not periodic
+// (Algorithm 4): digit order, T_j[y] = X_j[c] for y < n_j, c the integer of the
+// reduced output digits and y its n_j-digit bit reversal (the digits as the
+// generating matrix produces them).  Base b > 2: T_j[i] = X_j[i mod n_j] for
+// i < 2 n_j, X_j[rho] the value at residue rho.
 hipError_t launch_output_tables(const Geometry &G, const DevSpec &D, int r0, int nr, float *out,
                                 hipStream_t st);
 hipError_t launch_point_matrix(const Geometry &G, const DevSpec &D, int r, float *X, int64_t ldx,
@@ -204,7 +215,7 @@ hipError_t launch_leaf(const Geometry &G, int mode, const qmc_integrand &f, cons
                        const float *U, int nr, int r0, const float *A, int t, int64_t lda,
                        int64_t ldu, const LeafPlan &lp, const LeafOut &o, hipStream_t st);
 
-// Algorithm 4 (nets that are not periodic): one 64-point x 256-column tile per
+// Gather path (Algorithm 4 nets, base b > 2): one 64-point x 256-column tile per
 // workgroup (alg4_col_tiles(t) column tiles); modes kModeStoreY, kModeSum
 // (partial[r][point tile][column tile]) and kModePoint (ppart[r][column tile][N]).
 // tab: the digit-order value tables of launch_output_tables for the nr
@@ -212,9 +223,24 @@ hipError_t launch_leaf(const Geometry &G, int mode, const qmc_integrand &f, cons
 struct Alg4Out {
   float *Y;
   int64_t ldy;
+  int64_t ystride;  // StoreY: floats between the randomisations' outputs
   double *partial;
   float *ppart;
 };
+// One pass of the gather path: coordinates [j0, j0 + sc) over points n < npts,
+// optionally adding root[r][n mod nsplit][col] (leading dimension ldp, stride
+// root_stride per randomisation, nsplit >= 64) to every y before the epilogue.
+// Base b > 2 splits the product in two passes (the grouped cascade of
+// Algorithm 2 at one level): the upper coordinates (n_j <= nsplit) over the
+// nsplit residues into the root table, then the lower ones over all N points.
+struct Alg4Pass {
+  int32_t j0, sc;
+  int64_t npts;
+  const float *root;
+  int64_t ldp, root_stride, nsplit;
+  const char *timer;  // launch-timer name
+};
+Alg4Pass alg4_whole(const Geometry &G);  // one pass over every coordinate and point
 int64_t alg4_point_tiles(const Geometry &G);
 int64_t alg4_index_words(const Geometry &G);  // (64 + tiles) * s
 int alg4_col_tiles(int t);
@@ -224,7 +250,7 @@ hipError_t launch_alg4_index(const Geometry &G, const uint32_t *gen, const int32
                              uint32_t *ylo, uint32_t *ytile, hipStream_t st);
 hipError_t launch_alg4(const Geometry &G, const DevSpec &D, int mode, const qmc_integrand &f,
                        int prec, const float *tab, int nr, const float *A, int t, int64_t lda,
-                       const Alg4Out &o, hipStream_t st);
+                       const Alg4Pass &ps, const Alg4Out &o, hipStream_t st);
 
 // Q[r] = scale * sum of partial[r][*] (fixed order, compensated).
 hipError_t launch_reduce(const double *partial, int nr, int64_t per, double scale, double *Q,

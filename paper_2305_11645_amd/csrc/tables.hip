@@ -1,15 +1,16 @@
 // Point-table generation (the distinct values of every coordinate).
 //
-// For coordinate j with n_j = 2^nb distinct values the integer c of the value
-// c / 2^nb at residue rho < n_j is
-//   lattice       c = rho * z'_j mod 2^nb                      (Section 1.3)
+// For coordinate j with n_j = b^nb distinct values the integer c of the value
+// c / n_j at residue rho < n_j is
+//   lattice       c = rho * z'_j mod n_j                       (Section 1.3)
 //   poly lattice  c = int(rho(x) g'_j(x) mod x^nb)             (Section 1.1, nu)
 //   digital net   digits y_p = sum_q C_{p,q} rho_q (p <= nb)   (eq. def:digital,
 //                 c = sum_p y_p 2^{nb-p}                        reduced_genmat_net2)
-// then the randomisation and the map are applied in FP64 (Section 1.2,
-// Section 2.3) and the result is rounded once to FP32.  All integer work is
-// exact; the FP64 sequence is fixed (no contraction) so tables are
-// reproducible bit for bit.
+// (polynomial lattices and nets in base 2), then the randomisation and the map
+// are applied in FP64 (Section 1.2, Section 2.3) and the result is rounded
+// once to FP32.  All integer work is exact; c / n_j is exact for b = 2 and one
+// correctly rounded division otherwise; the FP64 sequence is fixed (no
+// contraction) so tables are reproducible bit for bit.
 #include <algorithm>
 
 #include "qmc_internal.h"
@@ -20,13 +21,19 @@ namespace qmc {
 
 // The point-set constants the value computation needs.
 struct PointConsts {
-  int32_t m, s, kind, rand, map;
+  int32_t m, s, kind, rand, map, b;
   int32_t by_output;    // rho is already the integer c of the value c / 2^nb (value tables of nets)
   int32_t nonperiodic;  // a reduced net that depends on every input digit
 };
 
 static PointConsts consts_of(const Geometry &G) {
-  return PointConsts{G.m, G.s, G.kind, G.rand, G.map, 0, G.nonperiodic};
+  return PointConsts{G.m, G.s, G.kind, G.rand, G.map, G.b, 0, G.nonperiodic};
+}
+
+__host__ __device__ __forceinline__ uint64_t ipow_u64(uint32_t b, int e) {
+  uint64_t r = 1;
+  for (int i = 0; i < e; ++i) r *= b;
+  return r;
 }
 
 // The integer c of the value c / 2^nb of coordinate j at input index rho:
@@ -40,6 +47,7 @@ __device__ __forceinline__ uint32_t value_int(const PointConsts &G, const uint32
   if (nb == 0) return 0u;
   const uint32_t mask = (nb >= 32) ? 0xffffffffu : ((1u << nb) - 1u);
   if (G.by_output) return rho & mask;
+  if (G.kind == QMC_LATTICE && G.b != 2) return (uint32_t)(((uint64_t)rho * gen[j]) % ipow_u64(G.b, nb));
   if (G.kind == QMC_LATTICE) return (rho * gen[j]) & mask;
   if (G.kind == QMC_POLY_LATTICE) {
     const uint32_t g = gen[j];
@@ -117,7 +125,8 @@ __device__ __forceinline__ double value_f64(const PointConsts &G, const DevSpec 
     x = (double)(2 * U + 1) * 0x1p-53;  // exact
   } else {
     const uint32_t c = value_int(G, D.gen, j, rho, nb);
-    x = (double)c * __builtin_ldexp(1.0, -nb);  // exact
+    x = G.b == 2 ? (double)c * __builtin_ldexp(1.0, -nb)  // exact
+                 : __ddiv_rn((double)c, (double)ipow_u64(G.b, nb));
     if (G.rand == QMC_RANDOM_SHIFT) {
       x = __dadd_rn(x, D.shift[(size_t)r * G.s + j]);
       if (x >= 1.0) x = __dsub_rn(x, 1.0);
@@ -205,21 +214,23 @@ __global__ __launch_bounds__(256) void tables_kernel(TabArgs ta, DevSpec D, int 
 
 template <bool INVNORM>
 __global__ void values_kernel(PointConsts G, DevSpec D, int r, int j, int nb, double *__restrict__ out) {
-  const uint32_t n = 1u << nb;
+  const uint32_t n = (uint32_t)ipow_u64(G.b, nb);
   for (uint32_t rho = blockIdx.x * blockDim.x + threadIdx.x; rho < n; rho += gridDim.x * blockDim.x)
     out[rho] = value_f64<INVNORM>(G, D, r, j, rho, nb);
 }
 
 template <bool INVNORM>
 __global__ void point_matrix_kernel(PointConsts G, DevSpec D, int r, float *__restrict__ X, int64_t ldx) {
-  const int64_t total = ((int64_t)1 << G.m) * G.s;
+  const int64_t total = (int64_t)ipow_u64(G.b, G.m) * G.s;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
        idx += (int64_t)gridDim.x * blockDim.x) {
     const int64_t k = idx / G.s;
     const int j = (int)(idx - k * G.s);
     const int nb = D.nbj[j];
     // a net that is not periodic needs every digit of k
-    const uint32_t rho = G.nonperiodic ? (uint32_t)k : (uint32_t)(k & ((int64_t(1) << nb) - 1));
+    const uint32_t rho = G.nonperiodic ? (uint32_t)k
+                         : G.b == 2    ? (uint32_t)(k & ((int64_t(1) << nb) - 1))
+                                       : (uint32_t)(k % (int64_t)ipow_u64(G.b, nb));
     X[k * ldx + j] = (float)value_f64<INVNORM>(G, D, r, j, rho, nb);
   }
 }
@@ -274,7 +285,7 @@ hipError_t launch_point_values(const Geometry &G, const DevSpec &D, int r, int j
   int nb = 0;
   for (int I = 0; I <= G.m; ++I)
     if (j >= G.lev[I].j0 && j < G.lev[I].j0 + G.lev[I].tau) nb = G.lev[I].nb;
-  const dim3 grid(grid_for(int64_t(1) << nb, 256));
+  const dim3 grid(grid_for((int64_t)ipow_u64(G.b, nb), 256));
   PointConsts pc = consts_of(G);
   pc.by_output = G.nonperiodic;  // such a net's values are listed by their output digits
   if (G.map == QMC_MAP_INVNORM)
@@ -295,11 +306,14 @@ hipError_t launch_point_matrix(const Geometry &G, const DevSpec &D, int r, float
   return hipGetLastError();
 }
 
-// Value tables indexed by output digits (Algorithm 4): for every coordinate j
-// and c < n_j, out[(r - r0) * total + soff[j] + c] = X_j[c] in FP32.  The
-// flat index is mapped to its coordinate by a binary search over soff.
+// Value tables of the gather path (layout at launch_output_tables' declaration):
+// every value X_j(rho), rho < n_j, of every coordinate is computed once; the
+// flat index e over sum_j n_j is mapped to (j, rho) by a binary search over
+// soff.  Nets (digit order): rho is the digit word y, stored at aoff_j + y,
+// the value that of the output integer bitreverse(y).  Base b > 2: rho is the
+// residue, stored at aoff_j + rho and aoff_j + rho + n_j.
 template <bool INVNORM>
-__global__ __launch_bounds__(256) void outvals_kernel(PointConsts G, DevSpec D, int r0,
+__global__ __launch_bounds__(256) void outvals_kernel(PointConsts G, DevSpec D, int r0, int64_t stride,
                                                       float *__restrict__ out) {
   const int rl = blockIdx.y;
   const int64_t total = D.sample_total;
@@ -310,9 +324,17 @@ __global__ __launch_bounds__(256) void outvals_kernel(PointConsts G, DevSpec D, 
       if (D.soff[mid] <= e) lo = mid; else hi = mid - 1;
     }
     const int nb = D.nbj[lo];
-    const uint32_t y = (uint32_t)(e - D.soff[lo]);  // digit-order index
-    const uint32_t c = nb == 0 ? 0u : __builtin_bitreverse32(y) >> (32 - nb);
-    out[(int64_t)rl * total + D.aoff[lo] + y] = (float)value_f64<INVNORM>(G, D, r0 + rl, lo, c, nb);
+    const uint32_t y = (uint32_t)(e - D.soff[lo]);
+    float *o = out + (int64_t)rl * stride + D.aoff[lo];
+    if (G.b == 2) {
+      const uint32_t c = nb == 0 ? 0u : __builtin_bitreverse32(y) >> (32 - nb);
+      o[y] = (float)value_f64<INVNORM>(G, D, r0 + rl, lo, c, nb);
+    } else {
+      const int64_t n = (lo + 1 < G.s ? D.soff[lo + 1] : total) - D.soff[lo];
+      const float v = (float)value_f64<INVNORM>(G, D, r0 + rl, lo, y, nb);
+      o[y] = v;
+      o[y + n] = v;
+    }
   }
 }
 
@@ -320,12 +342,12 @@ hipError_t launch_output_tables(const Geometry &G, const DevSpec &D, int r0, int
                                 hipStream_t st) {
   LaunchTimer tm("tables", st);
   PointConsts pc = consts_of(G);
-  pc.by_output = 1;
+  pc.by_output = G.nonperiodic;  // nets: the value of an output integer
   const dim3 grid(grid_for(D.sample_total, 256), nr);
   if (G.map == QMC_MAP_INVNORM)
-    hipLaunchKernelGGL(outvals_kernel<true>, grid, dim3(256), 0, st, pc, D, r0, out);
+    hipLaunchKernelGGL(outvals_kernel<true>, grid, dim3(256), 0, st, pc, D, r0, G.gather_total, out);
   else
-    hipLaunchKernelGGL(outvals_kernel<false>, grid, dim3(256), 0, st, pc, D, r0, out);
+    hipLaunchKernelGGL(outvals_kernel<false>, grid, dim3(256), 0, st, pc, D, r0, G.gather_total, out);
   return hipGetLastError();
 }
 

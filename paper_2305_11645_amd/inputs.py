@@ -90,6 +90,18 @@ def w_logb(s: int, cap: int, b: int) -> np.ndarray:
     return np.array(out, dtype=np.int32)
 
 
+def w_logb_pow(s: int, cap: int, num: int, den: int, b: int) -> np.ndarray:
+    """w_j = min(cap, floor((num/den) * log_b(j+1))), exact: largest q with b^(q*den) <= (j+1)^num."""
+    out = []
+    for j in range(s):
+        n = (j + 1) ** num
+        q = 0
+        while b ** ((q + 1) * den) <= n:
+            q += 1
+        out.append(min(cap, q))
+    return np.array(out, dtype=np.int32)
+
+
 def w_log2_pow(s: int, cap: int, num: int, den: int) -> np.ndarray:
     """w_j = min(cap, floor((num/den) * log2(j+1))), exact: largest q with 2^(q*den) <= (j+1)^num."""
     out = []
@@ -206,6 +218,7 @@ CONFIG_NAMES = {
     5: "C5 shifted reduced lattice m=20 s=t=1024 cos-mean gradient",
     6: "C6 reduced Monte Carlo basket call m=20 s=t=512 R=4",
     7: "C7 digitally shifted reduced Sobol'-type net (Algorithm 4) m=16 s=t=512 R=2 Gaussian cos-mean",
+    8: "C8 shifted reduced lattice in base 3 m=10 (N=59049) s=t=256 R=8 cos-mean",
 }
 
 # Basket option of Section 5 (Black-Scholes, zero rate): S_j(0) = 100, T = 1,
@@ -218,7 +231,7 @@ BASKET_K = 110.0 / BASKET_SCALE
 
 def make_config(c: int, seed: int | None = None, *, m: int | None = None, s: int | None = None,
                 t: int | None = None, R: int | None = None, kind: int | None = None) -> Workload:
-    """Build workload C<c> (1..7).  Size overrides give the same recipe at other shapes."""
+    """Build workload C<c> (1..8).  Size overrides give the same recipe at other shapes."""
     if seed is None:
         seed = 1000 + c
     rng = np.random.default_rng(seed)
@@ -289,12 +302,25 @@ def make_config(c: int, seed: int | None = None, *, m: int | None = None, s: int
         g, cc, h, K = G_COS, 1.0, H_ID, 0.0
         A_fn = lambda: rng.standard_normal((s_, t_)) / math.sqrt(s_)
         prec = FP32
+    elif c == 8:
+        # C2's shape, integrand and w rule in base 3: w_j = floor(1.5 log_3(j+1)),
+        # capped at m - 2
+        b_ = 3
+        m_, s_, t_, R_ = 10, 256, 256, 8
+        m_, s_, t_, R_ = m or m_, s or s_, t or t_, R or R_
+        w = w_logb_pow(s_, max(m_ - 2, 0), 3, 2, b_)
+        kind_ = LATTICE if kind is None else kind
+        rand, mp = RANDOM_SHIFT, MAP_ID
+        g, cc, h, K = G_COS, 1.0, H_ID, 0.0
+        A_fn = lambda: rng.standard_normal((s_, t_)) / math.sqrt(s_)
+        prec = FP32
     else:
         raise ValueError(f"unknown workload C{c}")
+    b_ = b_ if c == 8 else 2
 
     nb = (m_ - np.minimum(w, m_)).astype(np.int64)
     if kind_ == LATTICE:
-        gen = draw_lattice(rng, nb)
+        gen = draw_lattice(rng, nb, b_)
     elif kind_ == POLY_LATTICE:
         gen = draw_poly(rng, nb)
     elif kind_ == DIGITAL_NET:
@@ -306,14 +332,14 @@ def make_config(c: int, seed: int | None = None, *, m: int | None = None, s: int
     A64 = np.ascontiguousarray(A_fn(), dtype=np.float64)
     shift = dshift = samples = None
     if kind_ == IID:
-        samples = draw_iid_samples(rng, R_, nb)
+        samples = draw_iid_samples(rng, R_, nb, b_)
     elif rand == RANDOM_SHIFT:
         shift = rng.random((R_, s_))
     elif rand == DIGITAL_SHIFT:
         dshift = rng.integers(0, 1 << 52, size=(R_, s_), dtype=np.uint64)
     else:
         R_ = 1
-    return Workload(name=CONFIG_NAMES[c], kind=kind_, b=2, m=m_, s=s_, t=t_, w=w,
+    return Workload(name=CONFIG_NAMES[c], kind=kind_, b=b_, m=m_, s=s_, t=t_, w=w,
                     gen=gen, rand=rand, R=R_, shift=shift, dshift=dshift, map=mp,
                     A64=A64, g=g, c=cc, h=h, K=K, prec=prec, samples=samples)
 

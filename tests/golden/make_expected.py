@@ -16,7 +16,8 @@ from oracle import oracle as O  # noqa: E402
 from paper_2305_11645_amd import inputs as I  # noqa: E402
 
 PRECISIONS = {1: [I.FP32], 2: [I.FP32, I.SPLIT_BF16X3], 3: [I.SPLIT_BF16X3, I.FP32],
-              4: [I.FP32, I.SPLIT_BF16X3], 5: [I.FP32], 6: [I.FP32], 7: [I.FP32, I.SPLIT_BF16X3]}
+              4: [I.FP32, I.SPLIT_BF16X3], 5: [I.FP32], 6: [I.FP32], 7: [I.FP32, I.SPLIT_BF16X3],
+              8: [I.FP32, I.SPLIT_BF16X3]}
 
 
 def main():

@@ -47,7 +47,7 @@ def _spec(wl, **over):
     dshift = over.pop("dshift", wl.dshift)
     samples = over.pop("samples", wl.samples)
     arrs["w"], arrs["gen"] = w, gen
-    sp = _lib.PointSpec(b=over.pop("b", 2), m=over.pop("m", wl.m), s=over.pop("s", wl.s),
+    sp = _lib.PointSpec(b=over.pop("b", wl.b), m=over.pop("m", wl.m), s=over.pop("s", wl.s),
                         kind=over.pop("kind", wl.kind),
                         w=w.ctypes.data_as(ct.POINTER(ct.c_int32)),
                         gen=gen.ctypes.data_as(ct.POINTER(ct.c_uint64)),
@@ -80,7 +80,6 @@ def lat(**kw):
 
 CASES = [
     ("b not prime", lambda wl: _spec(wl, b=4), 1),
-    ("b odd prime", lambda wl: _spec(wl, b=3), 2),
     ("m too large", lambda wl: _spec(wl, m=25), 2),
     ("m zero", lambda wl: _spec(wl, m=0), 2),
     ("w0 nonzero", lambda wl: _spec(wl, w=np.r_[1, wl.w[1:]]), 1),
@@ -99,6 +98,38 @@ CASES = [
 @pytest.mark.parametrize("name,make,code", CASES, ids=[c[0] for c in CASES])
 def test_points_init_validation(name, make, code):
     sp, keep = make(lat())
+    st, msg = _init_status(sp)
+    assert st == code, (name, st, msg)
+    assert msg
+
+
+def lat3(**kw):
+    return I.make_custom(kind=I.LATTICE, m=5, s=10, t=4, w=I.w_logb(10, 6, 3), rand=I.RANDOM_SHIFT, R=2,
+                         b=3, **kw)
+
+
+BASE_CASES = [
+    ("b = 3 digital net", lambda wl: _spec(wl, kind=I.DIGITAL_NET,
+                                           gen=np.ones(10 * 5, dtype=np.uint64)), 2),
+    ("b = 3 polynomial lattice", lambda wl: _spec(wl, kind=I.POLY_LATTICE), 2),
+    ("b = 3 digital shift", lambda wl: _spec(wl, rand=I.DIGITAL_SHIFT, shift=None,
+                                             dshift=np.zeros((2, 10), dtype=np.uint64)), 2),
+    ("b^m above 2^24", lambda wl: _spec(wl, m=16), 2),
+    ("generator divisible by b", lambda wl: _spec(wl, gen=np.r_[[3], wl.gen[1:]]), 1),
+    ("generator not below b^e", lambda wl: _spec(wl, gen=np.r_[[3 ** 5 + 1], wl.gen[1:]]), 1),
+    ("generator 2 is a unit mod 3^e", lambda wl: _spec(wl, gen=np.r_[[2], wl.gen[1:]]), 4),
+]
+
+
+@pytest.mark.parametrize("name,make,code", BASE_CASES, ids=[c[0] for c in BASE_CASES])
+def test_base_b_points_init_validation(name, make, code):
+    """A prime base b > 2 (Section 1.3): lattices and reduced Monte Carlo only,
+    N = b^m up to 2^24, generators z'_j units modulo b^{m-w_j} (code 4: the
+    spec is valid and the call reaches the device check, no GPU here)."""
+    import torch
+    if code == 4 and torch.cuda.is_available():
+        pytest.skip("a valid spec creates the point set on a GPU")
+    sp, keep = make(lat3())
     st, msg = _init_status(sp)
     assert st == code, (name, st, msg)
     assert msg

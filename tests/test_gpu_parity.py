@@ -1,7 +1,7 @@
 """GPU parity: the HIP library against the FP64 oracle, through the C ABI.
 
 Small cases compare every output element with the oracle (several tiles and a
-ragged column tail); the five full-size workloads compare sampled outputs that
+ragged column tail); the full-size workloads compare sampled outputs that
 the oracle computes one by one, and the estimates against oracle values stored
 by tests/golden/make_expected.py (a script that calls only the oracle).
 """
@@ -412,6 +412,138 @@ def test_alg4_gradient_is_unsupported():
         q.estimate_grad(pts, to_dev(wl.A, torch), q.Integrand_.of(wl))
 
 
+# ------------------------------------------------------------------ prime base b > 2 (Section 1.3, Section 4)
+
+BASE_B = [(3, 6), (5, 4), (7, 3)]   # N = 729, 625, 343
+
+
+def lat_b(b, m, rand=I.RANDOM_SHIFT, mp=I.MAP_ID, s=40, t=100, R=2, seed=8, kind=I.LATTICE, g=I.G_COS,
+          h=I.H_ID, K=0.0, c=1.0, A_scale=0.3):
+    R = R if rand != I.NO_SHIFT or kind == I.IID else 1
+    return I.make_custom(kind=kind, m=m, s=s, t=t, w=I.w_logb(s, m + 1, b), rand=rand, R=R, map=mp, g=g,
+                         h=h, K=K, c=c, seed=seed, A_scale=A_scale, b=b)
+
+
+def test_base_b_is_planned_for_gathered_tiles():
+    """A base b > 2 has N = b^m points and takes the gathered-tile path.  With
+    b = 3, m = 6, s = 40 (w_j = floor(log_3(j+1))) the split level L' = 2 is
+    the cheapest: in whole 32-coordinate steps plus 16 per point for the root
+    rows, 729 * 32 + 81 * 32 + 16 * 729 = 37584 against 729 * 32 + 243 * 64 +
+    16 * 729 = 50544 at L' = 1 and 729 * 64 = 46656 in one pass (L' = 3 would
+    leave 27 < 64 residues).  N = 27 has no split."""
+    torch_cuda()
+    wl = lat_b(3, 6)
+    pts = q.Points.from_workload(wl)
+    nb = wl.m - np.minimum(wl.w, wl.m)
+    assert pts.N == 3 ** 6 and pts.split_level == 2
+    assert pts.distinct_values == int(np.sum(3 ** nb))
+    assert q.Points.from_workload(lat_b(3, 3, s=7)).split_level == -1
+
+
+@pytest.mark.parametrize("b,m", BASE_B)
+@pytest.mark.parametrize("rand,mp", [(I.NO_SHIFT, I.MAP_ID), (I.RANDOM_SHIFT, I.MAP_CENTER),
+                                     (I.RANDOM_SHIFT, I.MAP_TENT), (I.RANDOM_SHIFT, I.MAP_INVNORM)])
+def test_base_b_tables_bit_exact(b, m, rand, mp):
+    """Section 1.3 in base b: the n_j = b^e values c / n_j of each coordinate
+    (one correctly rounded FP64 division), shifted and mapped, equal the
+    oracle's bit for bit (the inverse-normal map to 1e-14)."""
+    from oracle import oracle as O
+    torch_cuda()
+    wl = lat_b(b, m, rand, mp, s=24)
+    pts = q.Points.from_workload(wl)
+    for r in range(wl.R):
+        for j in range(wl.s):
+            got = q.point_values(pts, r, j).cpu().numpy()
+            ref = O.point_values(wl, r, j)
+            if mp == I.MAP_INVNORM:
+                np.testing.assert_allclose(got, ref, rtol=1e-14, atol=0)
+            else:
+                np.testing.assert_array_equal(got, ref)
+
+
+def test_base_b_point_matrix_matches_unreduced():
+    """The FP32 point matrix of a base-5 lattice equals the FP32 rounding of
+    the oracle's unreduced lattice {k b^{w_j} z'_j / b^m}."""
+    from oracle import oracle as O
+    torch_cuda()
+    wl = lat_b(5, 4, s=30)
+    pts = q.Points.from_workload(wl)
+    for r in range(wl.R):
+        np.testing.assert_array_equal(q.point_matrix(pts, r).cpu().numpy(),
+                                      O.point_matrix_unreduced(wl, r).astype(np.float32))
+
+
+@pytest.mark.parametrize("b,m", BASE_B)
+@pytest.mark.parametrize("prec", [I.FP32, I.SPLIT_BF16X3])
+def test_base_b_matvec_elementwise(b, m, prec):
+    """Base-b products Y = X A, every element within the FP32 (split-bf16)
+    bound: N not a multiple of the 64-point tile, a ragged column tail and a
+    coordinate count that is not a multiple of the 32-coordinate step."""
+    torch = torch_cuda()
+    wl = lat_b(b, m, s=45)
+    pts = q.Points.from_workload(wl)
+    A = to_dev(wl.A, torch)
+    for r in range(wl.R):
+        Y = q.reduced_matvec(pts, A, r=r, prec=prec).cpu().numpy()
+        rel = _check_Y(wl, Y, r, prec)
+        assert rel < (1e-6 if prec == I.FP32 else 2e-4)
+
+
+@pytest.mark.parametrize("b,m,s,t", [(3, 3, 7, 3), (3, 8, 70, 300), (11, 2, 20, 17)])
+def test_base_b_matvec_shapes(b, m, s, t):
+    """27 points (under one tile), 6561 points (102 tiles and a ragged one) with
+    two column tiles, and 121 points in base 11."""
+    torch = torch_cuda()
+    wl = lat_b(b, m, I.RANDOM_SHIFT, I.MAP_CENTER, s=s, t=t, R=1)
+    pts = q.Points.from_workload(wl)
+    Y = q.reduced_matvec(pts, to_dev(wl.A, torch), r=0).cpu().numpy()
+    _check_Y(wl, Y, 0, I.FP32)
+
+
+@pytest.mark.parametrize("g,h,c,mp", [(I.G_COS, I.H_ID, 1.0, I.MAP_ID), (I.G_EXP, I.H_ID, -0.7, I.MAP_CENTER),
+                                      (I.G_EXP, I.H_CALL, 0.2, I.MAP_INVNORM), (I.G_ID, I.H_ID, 1.0, I.MAP_TENT)])
+def test_base_b_estimate(g, h, c, mp):
+    """Estimates over a shifted base-3 lattice for every integrand family within 1e-6."""
+    from oracle import oracle as O
+    torch = torch_cuda()
+    K = 1.0 if h == I.H_CALL else 0.0
+    wl = lat_b(3, 7, I.RANDOM_SHIFT, mp, s=50, t=80, g=g, h=h, c=c, K=K)
+    pts = q.Points.from_workload(wl)
+    Q = q.estimate(pts, to_dev(wl.A, torch), q.Integrand_.of(wl)).cpu().numpy()
+    Qo, _ = O.estimate(wl)
+    assert np.all(np.abs(Q - Qo) <= Q_TOL * np.maximum(np.abs(Qo), 1e-3)), (Q, Qo)
+
+
+@pytest.mark.parametrize("mp", [I.MAP_ID, I.MAP_INVNORM])
+def test_base_b_reduced_monte_carlo(mp):
+    """Section 4 in base 3: the samples of coordinate j are read at n mod N_j;
+    tables bit for bit (the inverse-normal map to 1e-14), products element-wise
+    and the estimate within 1e-6."""
+    from oracle import oracle as O
+    torch = torch_cuda()
+    wl = lat_b(3, 6, I.NO_SHIFT, mp, s=40, t=100, R=3, kind=I.IID, g=I.G_EXP, c=0.3)
+    pts = q.Points.from_workload(wl)
+    for j in range(wl.s):
+        got, ref = q.point_values(pts, 1, j).cpu().numpy(), O.point_values(wl, 1, j)
+        if mp == I.MAP_INVNORM:
+            np.testing.assert_allclose(got, ref, rtol=1e-14, atol=0)
+        else:
+            np.testing.assert_array_equal(got, ref)
+    A = to_dev(wl.A, torch)
+    _check_Y(wl, q.reduced_matvec(pts, A, r=2).cpu().numpy(), 2, I.FP32)
+    Q = q.estimate(pts, A, q.Integrand_.of(wl)).cpu().numpy()
+    Qo, _ = O.estimate(wl)
+    assert np.all(np.abs(Q - Qo) <= Q_TOL * np.abs(Qo)), (Q, Qo)
+
+
+def test_base_b_gradient_is_unsupported():
+    torch = torch_cuda()
+    wl = lat_b(3, 6)
+    pts = q.Points.from_workload(wl)
+    with pytest.raises(q.QMCUnsupported):
+        q.estimate_grad(pts, to_dev(wl.A, torch), q.Integrand_.of(wl))
+
+
 # ------------------------------------------------------------------ full-size workloads
 
 def _expected():
@@ -420,7 +552,7 @@ def _expected():
         return json.load(fh)
 
 
-@pytest.mark.parametrize("c", [1, 2, 3, 4, 5, 6, 7])
+@pytest.mark.parametrize("c", [1, 2, 3, 4, 5, 6, 7, 8])
 def test_full_config_estimate(c):
     """Each workload at its full size, in the launch configuration the
     benchmark times: Q[r] within 1e-6 relative of the stored oracle values."""
@@ -438,7 +570,7 @@ def test_full_config_estimate(c):
         assert rel.max() <= Q_TOL, (c, prec, rel)
 
 
-@pytest.mark.parametrize("c", [2, 3, 4, 5, 6])
+@pytest.mark.parametrize("c", [2, 3, 4, 5, 6, 8])
 def test_full_config_sampled_rows(c):
     """qmc_reduced_matvec at full size: 48 sampled rows of Y = X A against the
     oracle's FP64 rows (tables indexed by k mod n_j), element-wise bound."""
