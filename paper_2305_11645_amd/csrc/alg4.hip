@@ -51,6 +51,8 @@ struct Alg4Args {
   int32_t j0, sc;        // the pass sums coordinates [j0, j0 + sc)
   int64_t N, lda, ldy, tab_stride;  // N: points of the pass
   int64_t ntiles;        // ceil(N / 64)
+  int32_t nitems;        // ntiles x tct x randomisations
+  int32_t nsteps;        // 32-coordinate steps per item
   int64_t ystride;       // StoreY: floats between the randomisations' outputs
   const float *root;     // optional root table added to y: row n mod nsplit
   int64_t ldp, root_stride, nsplit;
@@ -69,60 +71,110 @@ __device__ __forceinline__ float load_f32(__amdgpu_buffer_rsrc_t r, uint32_t byt
 
 // IDX: how a point's value index combines the tile word and the lane word
 // (0: XOR, nets that are not periodic; 1: add, base b > 2).
-// (FP32 nets run at three waves per SIMD; the root-table epilogue of the add
-// index needs the registers of two.)
-template <int PREC, int MODE, int GF, int IDX>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC == QMC_FP32 && !IDX ? 3 : 2))) void alg4_kernel(Alg4Args a, DevSpec D, const float *__restrict__ tab,
-                                                   const float *__restrict__ A, float *__restrict__ Y,
-                                                   double *__restrict__ partial,
-                                                   float *__restrict__ ppart) {
+//
+// Work items are (64-point tile tn, 256-column tile ct, randomisation rl),
+// item = tn + ntiles (ct + tct rl).  A workgroup takes a contiguous range of
+// items, the ranges of the workgroups on one XCD adjacent (workgroup b runs on
+// XCD b mod 8), so each XCD's L2 holds the tables, rows of A and root rows of
+// its own part.  The steps of all its items form one stream: the loads of the
+// next step, which may belong to the next item, are in flight during this
+// step's products and the finished item's epilogue.
+// (FP32 nets run at three waves per SIMD; the other variants need the
+// registers of two.)
+// STREAM: a workgroup streams a range of short items (see above); otherwise it
+// takes the one item blockIdx.x and runs its steps two per loop iteration.
+template <int PREC, int MODE, int GF, int IDX, bool STREAM>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC == QMC_FP32 && !IDX ? 3 : 2))) void alg4_kernel(
+    Alg4Args a, DevSpec D, const float *__restrict__ tab, const float *__restrict__ A, float *__restrict__ Y,
+    double *__restrict__ partial, float *__restrict__ ppart) {
   __shared__ float Xs[2][TM * XPAD];  // point values, two steps: [point][coordinate]
   __shared__ double red[NWAVE];
   __shared__ float rsum[NWAVE][TM];
 
-  const int tn = blockIdx.x, ct = blockIdx.y, rl = blockIdx.z;
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wc = w * 64;
-  const int64_t n0 = (int64_t)tn * TM;
-  const __amdgpu_buffer_rsrc_t trs = raw_rsrc(tab + (int64_t)rl * a.tab_stride, (uint32_t)(a.tab_stride * 4));
-  const uint32_t *ytile = D.ytile + (int64_t)tn * a.s;  // the tile words of every coordinate
+  int i0, i1;
+  if constexpr (STREAM) {
+    const int nwg = gridDim.x;  // a multiple of 8
+    const int rank = (blockIdx.x & 7) * (nwg >> 3) + (blockIdx.x >> 3);
+    i0 = (int)((int64_t)rank * a.nitems / nwg);
+    i1 = (int)((int64_t)(rank + 1) * a.nitems / nwg);
+  } else {
+    i0 = blockIdx.x;
+    i1 = min(i0 + 1, a.nitems);
+  }
+  if (i0 >= i1) return;
+  const int nst = a.nsteps;          // steps per item
+  const int total = (i1 - i0) * nst;  // steps of this workgroup
+  // A position in the stream: step p, coordinate offset k0 inside item
+  // (tn, ct, rl).  Cursors advance one step at a time and stop at the last.
+  struct Cursor {
+    int p, k0, tn, ct, rl;
+  };
+  Cursor cur;
+  {
+    const int rest = i0 / (int)a.ntiles;
+    cur = Cursor{0, 0, i0 - rest * (int)a.ntiles, rest % a.tct, rest / a.tct};
+  }
+  auto advance = [&](Cursor c) {
+    if (c.p + 1 >= total) return c;
+    ++c.p;
+    c.k0 += TK;
+    if (c.k0 == nst * TK) {
+      c.k0 = 0;
+      if (++c.tn == (int)a.ntiles) {
+        c.tn = 0;
+        if (++c.ct == a.tct) {
+          c.ct = 0;
+          ++c.rl;
+        }
+      }
+    }
+    return c;
+  };
 
   // Only wave w reads columns [wc, wc + 64) of the tile, so its B operands come
   // straight from A into registers, one step ahead.  Element e < TK of a lane:
-  // row k0 + brow(e) + bh, column colc[bblk(e)] (FP32 32x32x2: e = kk + c,
+  // row k0 + brow(e) + bh, column bblk(e) (FP32 32x32x2: e = kk + c,
   // bh = lane / 32; BF16 32x32x16: e = kc + 8 c + q, bh = 8 (lane / 32)).
-  // Columns past t read column t - 1 (their outputs are dropped); rows past s
-  // read zero (the step's buffer ends at row s).
+  // Columns past t read column t - 1 (their outputs are dropped); rows past the
+  // pass's coordinates read zero (the step's buffer ends there).
   auto brow = [&](int e) { return PREC == QMC_FP32 ? (e & ~1) : (e & ~15) + (e & 7); };
   auto bblk = [&](int e) { return PREC == QMC_FP32 ? (e & 1) : ((e >> 3) & 1); };
   const int bh = PREC == QMC_FP32 ? (lane >> 5) : 8 * (lane >> 5);
-  uint32_t boff[2];  // byte offset of this lane's element in row k0 of the step
-#pragma unroll
-  for (int c = 0; c < 2; ++c)
-    boff[c] = (uint32_t)(((int64_t)bh * a.lda + min(ct * TN + wc + 32 * c + (lane & 31), a.t - 1)) * 4);
 
-  // Step k0: wave w gathers coordinates j0 + k0 + KPW w + q (q < KPW) of the 64
-  // points (lane = point); a value's byte offset is 4 (ytile_j op ylo_j(lane)).
-  // Coordinates past the pass's last gather that one (its rows of A read zero),
-  // points past N gather valid values (their outputs are dropped).
+  // Step p: wave w gathers coordinates j0 + k0 + KPW w + q (q < KPW) of the 64
+  // points of its item (lane = point); a value's byte offset is
+  // 4 (ytile_j op ylo_j(lane)).  Coordinates past the pass's last gather that
+  // one (its rows of A read zero), points past N gather valid values (their
+  // outputs are dropped).
   uint32_t yl[KPW], yt[KPW];  // index words of the next coordinates to gather
   float xv[KPW];
-  auto load_index = [&](int k0) {
+  auto load_index = [&](const Cursor &c) {
+    const uint32_t *ytile = D.ytile + (int64_t)c.tn * a.s;
 #pragma unroll
     for (int q = 0; q < KPW; ++q) {
-      const int j = a.j0 + min(k0 + KPW * w + q, a.sc - 1);
+      const int j = a.j0 + min(c.k0 + KPW * w + q, a.sc - 1);
       yl[q] = D.ylo[(int64_t)j * 64 + lane];
       yt[q] = ytile[j];
     }
   };
-  auto load_values = [&](int k0, float (&b)[TK]) {
+  // pad: a step past the stream (its rows of A read zero)
+  auto load_values = [&](const Cursor &c, bool pad, float (&b)[TK]) {
+    const int k0 = c.k0, ct = c.ct;
+    const __amdgpu_buffer_rsrc_t trs = raw_rsrc(tab + (int64_t)c.rl * a.tab_stride, (uint32_t)(a.tab_stride * 4));
 #pragma unroll
     for (int q = 0; q < KPW; ++q) xv[q] = load_f32(trs, (IDX ? yt[q] + yl[q] : yt[q] ^ yl[q]) << 2);
-    const int64_t left = (int64_t)a.sc - k0;  // rows of A from row k0 on
+    // rows of A from row k0 on
+    const int64_t left = pad ? 0 : (int64_t)a.sc - k0;
     const int64_t want = ((left - 1) * a.lda + a.t) * 4;
     const uint32_t bytes = left <= 0 ? 0u : want > 0xffffffffll ? 0xffffffffu : (uint32_t)want;
     const __amdgpu_buffer_rsrc_t ars = raw_rsrc(left <= 0 ? A : A + (int64_t)k0 * a.lda, bytes);
+    uint32_t boff[2];  // byte offset of this lane's element in row k0 of the step
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+      boff[c] = (uint32_t)(((int64_t)bh * a.lda + min(ct * TN + wc + 32 * c + (lane & 31), a.t - 1)) * 4);
 #pragma unroll
     for (int e = 0; e < TK; ++e) b[e] = load_f32(ars, (uint32_t)(brow(e) * a.lda * 4) + boff[bblk(e)]);
   };
@@ -131,11 +183,36 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC == QMC
     for (int q = 0; q < KPW; ++q) xs[lane * XPAD + KPW * w + q] = xv[q];
   };
 
+  // The accumulators start an item at zero, or (base b > 2 with a root table)
+  // at the upper levels' sum P[n mod nsplit] of its points (nsplit >= 64), read
+  // straight into them.
+  auto row_of = [&](int i, int v) { return 32 * i + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3); };
   f32x16 acc[2][2];
+  auto init_acc = [&](const Cursor &c) {
+    if (IDX && a.root) {
+      const __amdgpu_buffer_rsrc_t rrs =
+          raw_rsrc(a.root + (int64_t)c.rl * a.root_stride, (uint32_t)(a.nsplit * a.ldp * 4));
+      const int base = (int)(((int64_t)c.tn * TM) % a.nsplit);
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+      for (int cc = 0; cc < 2; ++cc) {
+        const uint32_t col = (uint32_t)min(c.ct * TN + wc + 32 * cc + (lane & 31), a.t - 1);
 #pragma unroll
-    for (int c = 0; c < 2; ++c) acc[i][c] = f32x16{0};
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int v = 0; v < 16; ++v) {
+            int p = base + row_of(i, v);
+            if (p >= a.nsplit) p -= (int)a.nsplit;
+            acc[i][cc][v] = load_f32(rrs, ((uint32_t)p * (uint32_t)a.ldp + col) * 4u);
+          }
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int cc = 0; cc < 2; ++cc) acc[i][cc] = f32x16{0};
+    }
+  };
+  init_acc(cur);
 
   auto products = [&](const float *xs, const float (&b)[TK]) {
     if (PREC == QMC_FP32) {
@@ -184,122 +261,148 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC == QMC
       }
     }
   };
-  // one step, without branches: the next step's gathers and rows of A and the
-  // index words of the step after are issued before this step's products; one
-  // barrier per step (the X tile is double-buffered)
-  auto step = [&](int k0, const float (&bcur)[TK], float (&bnext)[TK], const float *xcur, float *xnext) {
-    load_values(k0 + TK, bnext);
-    load_index(k0 + 2 * TK);
-    products(xcur, bcur);
-    store_x(xnext);
-    __syncthreads();
+
+  // The finished item's outputs; acc[i][c][v] is element (32 i + 8 (v / 4) +
+  // 4 (lane / 32) + v % 4, wc + 32 c + lane % 32) of its tile.
+  auto epilogue = [&](const Cursor &c) {
+    const int tn = c.tn, ct = c.ct, rl = c.rl;
+    const int64_t n0 = (int64_t)tn * TM;
+    const int colw = ct * TN + wc + (lane & 31);
+    if (MODE == kModeStoreY) {
+      float *Yr = Y + (int64_t)rl * a.ystride;
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+          for (int v = 0; v < 16; ++v) {
+            const int64_t row = n0 + row_of(i, v);
+            const int col = colw + 32 * c;
+            if (row < a.N && col < a.t) Yr[row * a.ldy + col] = a.sigma * acc[i][c][v];
+          }
+    } else {
+      float gv[2][2][16];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+          for (int v = 0; v < 16; ++v) {
+            const bool ok = n0 + row_of(i, v) < a.N && colw + 32 * c < a.t;
+            gv[i][c][v] = ok ? g_val<GF>(a.sigma * acc[i][c][v]) : 0.f;
+          }
+      if (MODE == kModeSum) {
+        float sl = 0.f;
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) sl += gv[i][c][v];
+        double d = (double)sl;
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) d += __shfl_xor(d, o, 64);
+        if (lane == 0) red[w] = d;
+        __syncthreads();
+        if (tid == 0)
+          partial[((int64_t)rl * a.ntiles + tn) * a.tct + ct] = ((red[0] + red[1]) + red[2]) + red[3];
+      } else {
+        // kModePoint: per row, the sum over this wave's 64 columns (both column
+        // blocks, then the 32 lanes with equal lane / 32), then over the 4 waves
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int v = 0; v < 16; ++v) {
+            float r = gv[i][0][v] + gv[i][1][v];
+#pragma unroll
+            for (int o = 16; o >= 1; o >>= 1) r += __shfl_xor(r, o, 64);
+            if ((lane & 31) == 0) rsum[w][row_of(i, v)] = r;
+          }
+        __syncthreads();
+        if (tid < TM && n0 + tid < a.N)
+          ppart[((int64_t)rl * a.tct + ct) * a.N + n0 + tid] =
+              ((rsum[0][tid] + rsum[1][tid]) + rsum[2][tid]) + rsum[3][tid];
+      }
+    }
   };
 
-  float b0[TK], b1[TK];
-  load_index(0);
-  load_values(0, b0);
-  load_index(TK);
-  store_x(Xs[0]);
-  __syncthreads();
-  // steps past the pass's coordinates multiply zero rows of A
-  for (int k0 = 0; k0 < a.sc; k0 += 2 * TK) {
-    step(k0, b0, b1, Xs[0], Xs[1]);
-    step(k0 + TK, b1, b0, Xs[1], Xs[0]);
-  }
-
-  // epilogue: acc[i][c][v] is element (32 i + 8 (v / 4) + 4 (lane / 32) + v % 4,
-  // wc + 32 c + lane % 32) of the tile
-  auto row_of = [&](int i, int v) { return 32 * i + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3); };
-  const int colw = ct * TN + wc + (lane & 31);
-  if (IDX && a.root) {  // the upper levels' sum, P[n mod nsplit] (nsplit >= 64; base b > 2 only)
-    const float *rt = a.root + (int64_t)rl * a.root_stride;
-    const int64_t base = n0 % a.nsplit;
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        int64_t p = base + row_of(i, v);
-        if (p >= a.nsplit) p -= a.nsplit;
-#pragma unroll
-        for (int c = 0; c < 2; ++c) acc[i][c][v] += rt[p * a.ldp + min(colw + 32 * c, a.t - 1)];
-      }
-  }
-  if (MODE == kModeStoreY) {
-    Y += (int64_t)rl * a.ystride;
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int c = 0; c < 2; ++c)
-#pragma unroll
-        for (int v = 0; v < 16; ++v) {
-          const int64_t row = n0 + row_of(i, v);
-          const int col = colw + 32 * c;
-          if (row < a.N && col < a.t) Y[row * a.ldy + col] = a.sigma * acc[i][c][v];
-        }
-    return;
-  }
-  float gv[2][2][16];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int c = 0; c < 2; ++c)
-#pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const bool ok = n0 + row_of(i, v) < a.N && colw + 32 * c < a.t;
-        gv[i][c][v] = ok ? g_val<GF>(a.sigma * acc[i][c][v]) : 0.f;
-      }
-  if (MODE == kModeSum) {
-    float sl = 0.f;
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int c = 0; c < 2; ++c)
-#pragma unroll
-        for (int v = 0; v < 16; ++v) sl += gv[i][c][v];
-    double d = (double)sl;
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) d += __shfl_xor(d, o, 64);
-    if (lane == 0) red[w] = d;
+  // one step: the next step's gathers and rows of A and the index words of the
+  // step after are issued first; then this step's products, the epilogue when
+  // it ends an item, the next step's point values into the other X buffer and
+  // one barrier (the X tile is double-buffered)
+  // cur: this step; nv: the next (its values and rows of A); ni: the one after
+  // (its index words).  Each step issues nv's and ni's loads, runs cur's
+  // products, the epilogue when cur ends an item, stores nv's point values into
+  // the other X buffer (one barrier per step: the X tile is double-buffered)
+  // and moves nv's rows of A, which have arrived by then, into the current set.
+  float bc[TK], bn[TK];
+  if constexpr (STREAM) {
+    Cursor nv = advance(cur), ni = advance(nv);
+    load_index(cur);
+    load_values(cur, false, bc);
+    load_index(nv);
+    store_x(Xs[0]);
     __syncthreads();
-    if (tid == 0)
-      partial[((int64_t)rl * a.ntiles + tn) * a.tct + ct] = ((red[0] + red[1]) + red[2]) + red[3];
-    return;
-  }
-  // kModePoint: per row, the sum over this wave's 64 columns (both column
-  // blocks, then the 32 lanes with equal lane / 32), then over the 4 waves
+    int xb = 0;
+    for (int p = 0; p < total; ++p) {
+      load_values(nv, p + 1 >= total, bn);
+      load_index(ni);
+      products(Xs[xb], bc);
+      if (cur.k0 == (nst - 1) * TK) {
+        epilogue(cur);
+        init_acc(nv);  // the next item's start (its root rows travel over the barrier)
+      }
+      store_x(Xs[xb ^ 1]);
+      __syncthreads();
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      float r = gv[i][0][v] + gv[i][1][v];
-#pragma unroll
-      for (int o = 16; o >= 1; o >>= 1) r += __shfl_xor(r, o, 64);
-      if ((lane & 31) == 0) rsum[w][row_of(i, v)] = r;
+      for (int e = 0; e < TK; ++e) bc[e] = bn[e];  // nv's rows of A have arrived
+      xb ^= 1;
+      cur = nv;
+      nv = ni;
+      ni = advance(ni);
     }
-  __syncthreads();
-  if (tid < TM && n0 + tid < a.N)
-    ppart[((int64_t)rl * a.tct + ct) * a.N + n0 + tid] =
-        ((rsum[0][tid] + rsum[1][tid]) + rsum[2][tid]) + rsum[3][tid];
+  } else {
+    // one item: steps k0 = 0, 32, ... two per iteration, the operand buffers
+    // swapped by name; steps past the pass's coordinates multiply zero rows
+    auto at = [&](int k0) { return Cursor{0, k0, cur.tn, cur.ct, cur.rl}; };
+    load_index(at(0));
+    load_values(at(0), false, bc);
+    load_index(at(TK));
+    store_x(Xs[0]);
+    __syncthreads();
+    auto step = [&](int k0, const float (&bcur)[TK], float (&bnext)[TK], const float *xcur, float *xnext) {
+      load_values(at(k0 + TK), false, bnext);
+      load_index(at(k0 + 2 * TK));
+      products(xcur, bcur);
+      store_x(xnext);
+      __syncthreads();
+    };
+    for (int k0 = 0; k0 < a.sc; k0 += 2 * TK) {
+      step(k0, bc, bn, Xs[0], Xs[1]);
+      step(k0 + TK, bn, bc, Xs[1], Xs[0]);
+    }
+    epilogue(cur);
+  }
 }
 
-template <int PREC, int MODE, int IDX>
-static void launch_g(int gf, dim3 grid, hipStream_t st, const Alg4Args &a, const DevSpec &D,
-                     const float *tab, const float *A, const Alg4Out &o) {
-#define QMC_ALG4(GF)                                                                                    \
-  hipLaunchKernelGGL((alg4_kernel<PREC, MODE, GF, IDX>), grid, dim3(256), 0, st, a, D, tab, A, o.Y, \
-                     o.partial, o.ppart)
-  if (gf == QMC_G_COS) QMC_ALG4(QMC_G_COS);
-  else if (gf == QMC_G_EXP) QMC_ALG4(QMC_G_EXP);
-  else QMC_ALG4(QMC_G_ID);
-#undef QMC_ALG4
+template <int PREC, int MODE, int IDX, bool STREAM>
+static const void *fn_g(int gf) {
+  if (gf == QMC_G_COS) return reinterpret_cast<const void *>(&alg4_kernel<PREC, MODE, QMC_G_COS, IDX, STREAM>);
+  if (gf == QMC_G_EXP) return reinterpret_cast<const void *>(&alg4_kernel<PREC, MODE, QMC_G_EXP, IDX, STREAM>);
+  return reinterpret_cast<const void *>(&alg4_kernel<PREC, MODE, QMC_G_ID, IDX, STREAM>);
 }
 
-template <int PREC, int IDX>
-static void launch_m(int mode, int gf, dim3 grid, hipStream_t st, const Alg4Args &a,
-                     const DevSpec &D, const float *tab, const float *A, const Alg4Out &o) {
-  if (mode == kModeStoreY) launch_g<PREC, kModeStoreY, IDX>(QMC_G_ID, grid, st, a, D, tab, A, o);
-  else if (mode == kModeSum) launch_g<PREC, kModeSum, IDX>(gf, grid, st, a, D, tab, A, o);
-  else launch_g<PREC, kModePoint, IDX>(gf, grid, st, a, D, tab, A, o);
+template <int PREC, int IDX, bool STREAM>
+static const void *fn_m(int mode, int gf) {
+  if (mode == kModeStoreY) return fn_g<PREC, kModeStoreY, IDX, STREAM>(QMC_G_ID);
+  if (mode == kModeSum) return fn_g<PREC, kModeSum, IDX, STREAM>(gf);
+  return fn_g<PREC, kModePoint, IDX, STREAM>(gf);
+}
+
+template <int PREC>
+static const void *fn_p(bool add, bool stream, int mode, int gf) {
+  if (add) return stream ? fn_m<PREC, 1, true>(mode, gf) : fn_m<PREC, 1, false>(mode, gf);
+  return stream ? fn_m<PREC, 0, true>(mode, gf) : fn_m<PREC, 0, false>(mode, gf);
 }
 
 }  // namespace
@@ -375,7 +478,7 @@ hipError_t launch_alg4(const Geometry &G, const DevSpec &D, int mode, const qmc_
   // byte offsets of a step's rows of A and of the value tables are 32-bit
   if (lda > kAlg4MaxLda || G.gather_total * 4 > 0xffffffffll) return hipErrorInvalidValue;
   if (ps.sc < 1 || ps.j0 < 0 || ps.j0 + ps.sc > G.s || ps.npts < 1 || ps.npts > G.N ||
-      (ps.root && ps.nsplit < TM))
+      (ps.root && (ps.nsplit < TM || ps.ldp < t || ps.nsplit * ps.ldp * 4 > 0xffffffffll)))
     return hipErrorInvalidValue;
   Alg4Args a{};
   a.m = G.m;
@@ -395,17 +498,28 @@ hipError_t launch_alg4(const Geometry &G, const DevSpec &D, int mode, const qmc_
   a.root_stride = ps.root_stride;
   a.nsplit = ps.nsplit;
   a.sigma = g_scale(f, mode);
-  A += (int64_t)ps.j0 * lda;
-  const dim3 grid((unsigned)a.ntiles, a.tct, nr);
+  const int64_t nitems = a.ntiles * a.tct * nr;
+  if (nitems > 0x7fffffffll) return hipErrorInvalidValue;
+  a.nitems = (int32_t)nitems;
+  a.nsteps = (int32_t)ceil_div(ps.sc, TK);
   const bool add = G.b != 2;
-  if (prec == QMC_FP32) {
-    if (add) launch_m<QMC_FP32, 1>(mode, f.g, grid, st, a, D, tab, A, o);
-    else launch_m<QMC_FP32, 0>(mode, f.g, grid, st, a, D, tab, A, o);
-  } else {
-    if (add) launch_m<QMC_SPLIT_BF16X3, 1>(mode, f.g, grid, st, a, D, tab, A, o);
-    else launch_m<QMC_SPLIT_BF16X3, 0>(mode, f.g, grid, st, a, D, tab, A, o);
-  }
-  return hipGetLastError();
+  const int gf = mode == kModeStoreY ? QMC_G_ID : f.g;
+  // Items of four or more steps hide their own start and end: one item per
+  // workgroup, scheduled by the hardware.  Shorter items (the lower pass of a
+  // base b > 2): one resident wave of workgroups (a multiple of 8, one share
+  // per XCD), each streaming a contiguous range of items.
+  const bool stream = a.nsteps < 4;
+  const void *fn = prec == QMC_FP32 ? fn_p<QMC_FP32>(add, stream, mode, gf) : fn_p<QMC_SPLIT_BF16X3>(add, stream, mode, gf);
+  int64_t wgs = nitems;
+  if (stream) wgs = round_up(std::min<int64_t>(nitems, std::max<int64_t>(resident_workgroups(fn, 256, 0), 8)), 8);
+  const float *Ap = A + (int64_t)ps.j0 * lda;
+  float *Y = o.Y;
+  double *partial = o.partial;
+  float *ppart = o.ppart;
+  DevSpec Dv = D;
+  void *args[] = {&a, &Dv, &tab, &Ap, &Y, &partial, &ppart};
+  const hipError_t e = hipLaunchKernel(fn, dim3((unsigned)wgs), dim3(256), args, 0, st);
+  return e != hipSuccess ? e : hipGetLastError();
 }
 
 }  // namespace qmc

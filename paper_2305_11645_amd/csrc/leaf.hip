@@ -523,7 +523,6 @@ __global__ __launch_bounds__(256) void leaf_kernel(LeafArgs a, const float *__re
 
 static size_t leaf_lds_bytes(const Geometry &G, int mode, int cpl, int nw);
 static const void *leaf_fn(const Geometry &G, int mode, int gf, int cpl);
-static int64_t resident_workgroups(const void *fn, int threads, size_t lds);
 
 LeafPlan leaf_plan(const Geometry &G, int t, int nr, int mode, int gf) {
   const int64_t tct = ceil_div(t, kTileT);
@@ -628,7 +627,7 @@ static size_t leaf_lds_bytes(const Geometry &G, int mode, int cpl, int nw) {
 }
 
 // Workgroups of a kernel instance that fit on the current device at once.
-static int64_t resident_workgroups(const void *fn, int threads, size_t lds) {
+int64_t resident_workgroups(const void *fn, int threads, size_t lds) {
   static std::mutex mu;
   static std::map<std::tuple<int, const void *, int, size_t>, int64_t> cache;
   int dev = 0;

@@ -210,6 +210,9 @@ struct LeafPlan {
   int cpl;             // columns of A per lane (the workgroup's tile is 64 cpl columns)
 };
 LeafPlan leaf_plan(const Geometry &G, int t, int nr, int mode, int gf);
+// Workgroups of kernel fn that fit on the current device at once (occupancy x
+// compute units), cached; 0 when the query fails.
+int64_t resident_workgroups(const void *fn, int threads, size_t lds);
 
 hipError_t launch_leaf(const Geometry &G, int mode, const qmc_integrand &f, const float *tables,
                        const float *U, int nr, int r0, const float *A, int t, int64_t lda,
