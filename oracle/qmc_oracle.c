@@ -29,9 +29,13 @@
  *     x = (2U + 1) 2^-53,  U = (c << (52 - n)) ^ delta;
  *   - the random shift is one IEEE FP64 addition followed by "subtract 1 if the
  *     sum is >= 1";
- *   - a prime base b > 2 is taken for lattices and reduced Monte Carlo, whose
- *     values c / b^e are one correctly rounded FP64 division; digital nets,
- *     polynomial lattices and the digital shift stay base 2;
+ *   - in a prime base b > 2 a value c / b^e is one correctly rounded FP64
+ *     division; polynomials and generating-matrix columns are the base-b
+ *     digits of the integers given (b = 2: the bit masks); the digital shift
+ *     adds the K base-b digits of an integer delta < b^K (b^K <= 2^52, most
+ *     significant first) digit by digit mod b and takes the midpoint of the
+ *     rest: x = (U + 1/2) / b^K (for b = 2, K = 52 and x = (2U + 1) 2^-53);
+ *     nets in base b > 2 must be periodic after reduction;
  *   - the inverse normal map is Wichura's algorithm AS241 (PPND16);
  *   - the integrand is f(y) = h(t^-1 sum_i g(y_i)) with g in {y, cos y,
  *     exp(c y)} and h in {u, max(0, u - K)}; h'(K) is taken as 0;
@@ -93,6 +97,58 @@ static uint64_t ipow(uint64_t b, int e) {
 
 static uint64_t n_of(const qo_spec *sp, int j) { return ipow((uint64_t)sp->b, nbits_of(sp, j)); }
 static int64_t N_of(const qo_spec *sp) { return (int64_t)ipow((uint64_t)sp->b, sp->m); }
+
+/* base-b digits of v, least significant first: d[i] = floor(v / b^i) mod b, i < n */
+static void digits_b(uint64_t v, uint64_t b, int n, int *d) {
+    for (int i = 0; i < n; ++i) { d[i] = (int)(v % b); v /= b; }
+}
+
+/* the integer sum_{i<n} d[i] b^i */
+static uint64_t undigits_b(const int *d, uint64_t b, int n) {
+    uint64_t v = 0;
+    for (int i = n - 1; i >= 0; --i) v = v * b + (uint64_t)d[i];
+    return v;
+}
+
+/* K: the number of base-b digits of the digital shift, the largest with b^K <= 2^52 */
+static int shift_digits(uint64_t b) {
+    int K = 0;
+    uint64_t v = 1;
+    while (v <= (UINT64_C(1) << 52) / b) { v *= b; ++K; }
+    return K;
+}
+
+/* F_b[x]: coefficients of a(x) g(x) mod x^e, a and g given by their base-b
+ * digits (coefficient i = digit i), returned as the integer with those digits */
+static uint64_t polymul_mod_b(uint64_t a, uint64_t g, int e, uint64_t b) {
+    int da[64], dg[64], dr[64];
+    digits_b(a, b, e, da);
+    digits_b(g, b, e, dg);
+    for (int i = 0; i < e; ++i) {
+        int acc = 0;
+        for (int k = 0; k <= i; ++k) acc = (acc + da[k] * dg[i - k]) % (int)b;
+        dr[i] = acc;
+    }
+    return undigits_b(dr, b, e);
+}
+
+/* Net over F_b: output digits y_p = sum_q C_{p,q} a_q mod b for p <= e (rows
+ * past e of the reduced matrix are zero), a_q the digits of a (q <= m); the
+ * column words hold C_{p,q} as base-b digit p-1.  Returns c = sum_{p<=e}
+ * y_p b^{e-p} (y_1 most significant). */
+static uint64_t netmul_b(const qo_spec *sp, int j, uint64_t a, int e) {
+    uint64_t b = (uint64_t)sp->b;
+    int m = sp->m, da[64], y[64] = {0}, col[64];
+    digits_b(a, b, m, da);
+    for (int q = 0; q < m; ++q) {
+        if (!da[q]) continue;
+        digits_b(sp->gen[(size_t)j * m + q], b, e, col);
+        for (int p = 0; p < e; ++p) y[p] = (y[p] + col[p] * da[q]) % (int)b;
+    }
+    uint64_t c = 0;
+    for (int p = 0; p < e; ++p) c = c * b + (uint64_t)y[p];
+    return c;
+}
 
 /* carry-less product of two F_2[x] polynomials given as bit masks, mod x^nb */
 static uint64_t clmul_mod(uint64_t a, uint64_t b, int nb) {
@@ -164,9 +220,21 @@ static double apply_map(const qo_spec *sp, double x) {
 /* Shift then map one coordinate value given as the integer c of c / b^nb. */
 static double shift_and_map(const qo_spec *sp, int r, int j, uint64_t c, int nb) {
     double x;
-    if (sp->rand == QO_DIGITAL_SHIFT) {                      /* b = 2 */
+    if (sp->rand == QO_DIGITAL_SHIFT && sp->b == 2) {
         uint64_t U = (c << (52 - nb)) ^ sp->dshift[(size_t)r * sp->s + j];
         x = (double)(2 * U + 1) * 0x1p-53;                  /* exact */
+    } else if (sp->rand == QO_DIGITAL_SHIFT) {
+        /* digits p = 1..K of x: those of c (p <= nb) plus those of delta, mod b */
+        uint64_t b = (uint64_t)sp->b;
+        int K = shift_digits(b), dc[64], dd[64], du[64];
+        digits_b(c, b, nb, dc);                               /* dc[nb - p] = digit p */
+        digits_b(sp->dshift[(size_t)r * sp->s + j], b, K, dd);  /* dd[K - p] = digit p */
+        for (int p = 1; p <= K; ++p) {
+            int yp = p <= nb ? dc[nb - p] : 0;
+            du[K - p] = (yp + dd[K - p]) % (int)b;
+        }
+        double U = (double)undigits_b(du, b, K);               /* exact, < 2^52 */
+        x = (U + 0.5) / (double)ipow(b, K);                    /* one rounding */
     } else {
         /* one correctly rounded division (exact for b = 2) */
         x = (double)c / (double)ipow((uint64_t)sp->b, nb);
@@ -227,6 +295,8 @@ static uint64_t reduced_int(const qo_spec *sp, int j, uint64_t rho) {
     int nb = nbits_of(sp, j);
     uint64_t mask = nb >= 64 ? ~UINT64_C(0) : ((UINT64_C(1) << nb) - 1);
     if (sp->kind == QO_LATTICE) return (uint64_t)(((unsigned __int128)rho * sp->gen[j]) % n_of(sp, j));
+    if (sp->b != 2 && sp->kind == QO_POLY_LATTICE) return polymul_mod_b(rho, sp->gen[j], nb, (uint64_t)sp->b);
+    if (sp->b != 2) return netmul_b(sp, j, rho, nb);
     if (sp->kind == QO_POLY_LATTICE) return clmul_mod(rho, sp->gen[j], nb);
     uint64_t y = 0;   /* digital net: XOR of the columns selected by the digits of rho */
     for (int q = 0; q < sp->m; ++q)
@@ -235,14 +305,17 @@ static uint64_t reduced_int(const qo_spec *sp, int j, uint64_t rho) {
     return bitrev(y, nb);
 }
 
-/* The bases taken here: b = 2 for every kind; a prime b > 2 for lattices and
- * reduced Monte Carlo, without a digital shift. */
+static int net_is_periodic(const qo_spec *sp);
+
+/* The bases taken here: b = 2 for every kind; a prime b > 2 for every kind
+ * except nets that are not periodic after reduction (and reduced Monte Carlo
+ * takes no shift in any base). */
 static int base_supported(const qo_spec *sp) {
     if (sp->b == 2) return 1;
     if (sp->b < 2) return 0;
     for (int d = 2; d * d <= sp->b; ++d)
         if (sp->b % d == 0) return 0;
-    return (sp->kind == QO_LATTICE || sp->kind == QO_IID) && sp->rand != QO_DIGITAL_SHIFT;
+    return sp->kind != QO_DIGITAL_NET || net_is_periodic(sp);
 }
 
 /* Distinct values X_j[rho], rho < n_j, of coordinate j for shift r (FP64). */
@@ -273,10 +346,19 @@ static uint64_t unreduced_int_over_N(const qo_spec *sp, int j, uint64_t k) {
     }
     if (sp->kind == QO_POLY_LATTICE) {
         if (w >= m) return 0;
+        if (sp->b != 2) {                      /* x^{w_j} g'_j: the digits shifted up by w */
+            uint64_t g = (uint64_t)(((unsigned __int128)sp->gen[j] * ipow((uint64_t)sp->b, w)) % (uint64_t)N_of(sp));
+            return polymul_mod_b(k, g, m, (uint64_t)sp->b);
+        }
         uint64_t g = sp->gen[j] << w;          /* x^{w_j} g'_j */
         return clmul_mod(k, g, m);
     }
     int nb = nbits_of(sp, j);
+    if (sp->b != 2) {
+        /* the reduced matrix (rows past nb zero) on all m digits of k, read as
+         * an integer over b^m: the nb leading digits, then m - nb zeros */
+        return netmul_b(sp, j, k, nb) * ipow((uint64_t)sp->b, m - nb);
+    }
     uint64_t y = 0;
     for (int q = 0; q < m; ++q) {
         uint64_t col = sp->gen[(size_t)j * m + q];
@@ -380,9 +462,13 @@ static int net_is_periodic(const qo_spec *sp) {
     if (sp->kind != QO_DIGITAL_NET) return 1;
     for (int j = 0; j < sp->s; ++j) {
         int nb = nbits_of(sp, j);
-        uint64_t mask = nb >= 64 ? ~UINT64_C(0) : ((UINT64_C(1) << nb) - 1);
-        for (int q = nb; q < sp->m; ++q)
-            if (sp->gen[(size_t)j * sp->m + q] & mask) return 0;
+        for (int q = nb; q < sp->m; ++q) {
+            uint64_t wd = sp->gen[(size_t)j * sp->m + q];
+            /* a column past nb with a nonzero digit in the first nb rows */
+            if (sp->b == 2 ? (nb >= 64 ? wd : wd & ((UINT64_C(1) << nb) - 1)) != 0
+                           : wd % ipow((uint64_t)sp->b, nb) != 0)
+                return 0;
+        }
     }
     return 1;
 }

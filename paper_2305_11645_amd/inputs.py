@@ -130,20 +130,53 @@ def draw_lattice(rng: np.random.Generator, nb: np.ndarray, b: int = 2) -> np.nda
     return z
 
 
-def draw_poly(rng: np.random.Generator, nb: np.ndarray) -> np.ndarray:
-    """g'_j as a bit mask of F_2 coefficients, degree < nb_j, constant term 1."""
-    return draw_lattice(rng, nb)  # same distribution over bit masks
+def draw_poly(rng: np.random.Generator, nb: np.ndarray, b: int = 2) -> np.ndarray:
+    """g'_j in F_b[x] with degree < nb_j and a nonzero constant term, given as
+    the integer g'_j(b) (coefficient i = base-b digit i; for b = 2 the bit mask
+    with constant term 1)."""
+    if b == 2:
+        return draw_lattice(rng, nb)  # same distribution over bit masks
+    g = np.ones(len(nb), dtype=np.uint64)
+    for j, n in enumerate(nb):
+        if n >= 1:
+            coef = [int(rng.integers(1, b))] + [int(rng.integers(0, b)) for _ in range(int(n) - 1)]
+            g[j] = np.uint64(sum(c * b ** i for i, c in enumerate(coef)))
+    return g
 
 
-def draw_net_lower(rng: np.random.Generator, s: int, m: int) -> np.ndarray:
-    """Random lower-triangular generating matrices over F_2 with unit diagonal.
+def shift_digits(b: int) -> int:
+    """K: the base-b digits of a digital shift, the largest with b^K <= 2^52."""
+    K = 0
+    while b ** (K + 1) <= 1 << 52:
+        K += 1
+    return K
+
+
+def draw_dshift(rng: np.random.Generator, R: int, s: int, b: int = 2) -> np.ndarray:
+    """Digital shifts: integers uniform below b^K, whose K base-b digits (most
+    significant first) are added to the point's digits mod b."""
+    if b == 2:
+        return rng.integers(0, 1 << 52, size=(R, s), dtype=np.uint64)
+    return rng.integers(0, b ** shift_digits(b), size=(R, s), dtype=np.uint64)
+
+
+def draw_net_lower(rng: np.random.Generator, s: int, m: int, b: int = 2) -> np.ndarray:
+    """Random lower-triangular generating matrices over F_b with a nonzero
+    diagonal (F_2: unit diagonal).
 
     Entry C_{p,q} (output digit p, input digit q, both 1-based) is zero for
-    q > p, one on the diagonal, and an independent fair bit below it.  Returned
-    as column words: word (j, q-1) has bit (p-1) set iff C^{(j)}_{p,q} = 1.
-    The full (unreduced) matrices are returned; the reduction by w is applied
-    by the consumer.
+    q > p, nonzero on the diagonal, and independent uniform below it.  Returned
+    as column words: word (j, q-1) holds C^{(j)}_{p,q} as its base-b digit p-1
+    (for b = 2, bit p-1).  The full (unreduced) matrices are returned; the
+    reduction by w is applied by the consumer.
     """
+    if b != 2:
+        words = np.zeros(s * m, dtype=np.uint64)
+        for j in range(s):
+            for q in range(m):
+                col = [0] * q + [int(rng.integers(1, b))] + [int(rng.integers(0, b)) for _ in range(m - q - 1)]
+                words[j * m + q] = np.uint64(sum(c * b ** p for p, c in enumerate(col)))
+        return words
     words = np.zeros(s * m, dtype=np.uint64)
     for j in range(s):
         bits = rng.integers(0, 2, size=(m, m))
@@ -356,13 +389,15 @@ def make_custom(*, kind: int, m: int, s: int, t: int, w: np.ndarray, rand: int =
     if kind == LATTICE:
         gen = draw_lattice(rng, nb, b)
     elif kind == POLY_LATTICE:
-        gen = draw_poly(rng, nb)
+        gen = draw_poly(rng, nb, b)
     elif kind == IID:
         gen = np.ones(s, dtype=np.uint64)  # unused
     elif net == "upper":
+        if b != 2:
+            raise ValueError("upper-triangular nets are drawn in base 2 only")
         gen = draw_net_upper(rng, s, m)
     else:
-        gen = draw_net_lower(rng, s, m)
+        gen = draw_net_lower(rng, s, m, b)
     A64 = rng.standard_normal((s, t)) * A_scale
     shift = dshift = samples = None
     if kind == IID:
@@ -372,7 +407,7 @@ def make_custom(*, kind: int, m: int, s: int, t: int, w: np.ndarray, rand: int =
     elif rand == RANDOM_SHIFT:
         shift = rng.random((R, s))
     elif rand == DIGITAL_SHIFT:
-        dshift = rng.integers(0, 1 << 52, size=(R, s), dtype=np.uint64)
+        dshift = draw_dshift(rng, R, s, b)
     else:
         R = 1
     return Workload(name="custom", kind=kind, b=b, m=m, s=s, t=t, w=w, gen=gen, rand=rand,

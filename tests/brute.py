@@ -8,6 +8,7 @@ Used to pin the oracle's point tables.
   polynomial   Sec. 1.1: x_k = nu(k(x) g_j(x) / x^m), g_j = x^{w_j} g'_j
   digital net  eq. def:digital with the reduced matrices of eq.
                reduced_genmat_net2: last min(w_j, m) rows of C^{(j)} set to 0
+               (polynomials and matrices over F_b, any prime b)
   reduced MC   Sec. 4, eq. randpts: the mixed-radix digits of n select the
                sample of each coordinate (greedy from the top digit down)
 """
@@ -22,19 +23,20 @@ from paper_2305_11645_amd.inputs import (DIGITAL_NET, DIGITAL_SHIFT, IID, LATTIC
                                          MAP_INVNORM, MAP_TENT, POLY_LATTICE, RANDOM_SHIFT)
 
 
-def digits(n: int, m: int) -> list[int]:
-    """b-adic digits of n, least significant first (b = 2)."""
-    return [(n >> q) & 1 for q in range(m)]
+def digits(n: int, m: int, b: int = 2) -> list[int]:
+    """b-adic digits of n, least significant first."""
+    return [(n // b ** q) % b for q in range(m)]
 
 
 def net_matrix(wl, j: int) -> list[list[int]]:
-    """C^{(j)} as an m x m 0/1 matrix: row p-1 = output digit p, column q-1 = input digit q."""
+    """C^{(j)} as an m x m matrix over F_b: row p-1 = output digit p, column
+    q-1 = input digit q; entry (p, q) is base-b digit p-1 of column word q-1."""
     m = wl.m
     C = [[0] * m for _ in range(m)]
     for q in range(m):
-        word = int(wl.gen[j * m + q])
+        col = digits(int(wl.gen[j * m + q]), m, wl.b)
         for p in range(m):
-            C[p][q] = (word >> p) & 1
+            C[p][q] = col[p]
     return C
 
 
@@ -56,6 +58,15 @@ def poly_mul_mod2(a: list[int], b: list[int]) -> list[int]:
     return out
 
 
+def poly_mul_modb(a: list[int], g: list[int], b: int) -> list[int]:
+    """Product in F_b[x] of two coefficient lists (lowest degree first)."""
+    out = [0] * (len(a) + len(g))
+    for i, ai in enumerate(a):
+        for k, gk in enumerate(g):
+            out[i + k] = (out[i + k] + ai * gk) % b
+    return out
+
+
 def unshifted_value(wl, k: int, j: int) -> Fraction:
     """The unreduced point definition, as an exact fraction in [0, 1)."""
     m, N = wl.m, wl.b ** wl.m
@@ -63,24 +74,39 @@ def unshifted_value(wl, k: int, j: int) -> Fraction:
     if wl.kind == LATTICE:
         z = (wl.b ** w) * int(wl.gen[j])
         return Fraction((k * z) % N, N)
+    b = wl.b
     if wl.kind == POLY_LATTICE:
-        gp = digits(int(wl.gen[j]), 64)
+        gp = digits(int(wl.gen[j]), 64 if b == 2 else m, b)
         g = [0] * w + gp                           # x^{w_j} g'_j(x)
-        f = poly_mul_mod2(digits(k, m), g)[:m]     # k(x) g_j(x) mod x^m
-        return sum((Fraction(f[i], 2 ** (m - i)) for i in range(m)), Fraction(0))
+        if b == 2:
+            f = poly_mul_mod2(digits(k, m), g)[:m]     # k(x) g_j(x) mod x^m
+        else:
+            f = poly_mul_modb(digits(k, m, b), g, b)[:m]
+        return sum((Fraction(f[i], b ** (m - i)) for i in range(m)), Fraction(0))
     C = reduced_net_matrix(wl, j)
-    n = digits(k, m)
-    y = [sum(C[p][q] * n[q] for q in range(m)) % 2 for p in range(m)]
-    return sum((Fraction(y[p], 2 ** (p + 1)) for p in range(m)), Fraction(0))
+    n = digits(k, m, b)
+    y = [sum(C[p][q] * n[q] for q in range(m)) % b for p in range(m)]
+    return sum((Fraction(y[p], b ** (p + 1)) for p in range(m)), Fraction(0))
 
 
-def digital_shift(x: Fraction, delta: int) -> float:
-    """Digit-wise XOR of the first 52 digits; the tail is replaced by its midpoint 2^-53."""
-    assert x.denominator & (x.denominator - 1) == 0 and x.denominator <= 2 ** 52
-    xd = [int((x * 2 ** (p + 1)) % 2 >= 1) for p in range(52)]     # digit p+1 of x
-    sd = [(delta >> (51 - p)) & 1 for p in range(52)]              # digit p+1 of delta / 2^52
-    val = sum((Fraction(xd[p] ^ sd[p], 2 ** (p + 1)) for p in range(52)), Fraction(0))
-    return float(val + Fraction(1, 2 ** 53))
+def shift_digits(b: int) -> int:
+    """K: the largest number of base-b digits with b^K <= 2^52 (52 for b = 2)."""
+    K = 0
+    while b ** (K + 1) <= 2 ** 52:
+        K += 1
+    return K
+
+
+def digital_shift(x: Fraction, delta: int, b: int = 2) -> float:
+    """Digit-wise addition mod b of the first K base-b digits of x and of delta
+    (delta's digits most significant first; XOR for b = 2); the tail is
+    replaced by its midpoint b^-K / 2."""
+    K = shift_digits(b)
+    assert (x * b ** K).denominator == 1
+    xd = [int(x * b ** (p + 1)) % b for p in range(K)]             # digit p+1 of x
+    sd = [(delta // b ** (K - 1 - p)) % b for p in range(K)]       # digit p+1 of delta / b^K
+    val = sum((Fraction((xd[p] + sd[p]) % b, b ** (p + 1)) for p in range(K)), Fraction(0))
+    return float(val + Fraction(1, 2 * b ** K))
 
 
 def randpts_index(wl, n: int, j: int) -> int:
@@ -104,7 +130,7 @@ def value(wl, r: int, k: int, j: int) -> float:
         off = sum(wl.b ** nb[i] for i in range(j))
         v = float(wl.samples[r, off + randpts_index(wl, k, j)])
     elif wl.rand == DIGITAL_SHIFT:
-        v = digital_shift(unshifted_value(wl, k, j), int(wl.dshift[r, j]))
+        v = digital_shift(unshifted_value(wl, k, j), int(wl.dshift[r, j]), wl.b)
     else:
         v = float(unshifted_value(wl, k, j))
         if wl.rand == RANDOM_SHIFT:

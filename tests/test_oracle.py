@@ -691,3 +691,94 @@ def test_base3_cos_mean_converges(oracle_lib):
     se = Q.std(ddof=1) / math.sqrt(len(Q))
     assert abs(Q.mean() - Iex) <= 4 * se
     assert se < 1e-3
+
+
+def test_base3_net_and_poly_example_golden(oracle_lib):
+    """The base-3 net and polynomial lattice worked by hand in
+    tests/golden/base3_net_poly_example.txt: the oracle's tables (n = 9 values,
+    indexed by k) give exactly those points."""
+    import dataclasses
+    O = oracle_lib
+    rows = [list(map(int, ln.split())) for ln in open(os.path.join(GOLDEN, "base3_net_poly_example.txt"))
+            if ln.strip() and not ln.startswith("#")]
+    assert len(rows) == 9
+    net = I.make_custom(kind=I.DIGITAL_NET, m=2, s=1, t=1, w=[0], seed=1, b=3)
+    net = dataclasses.replace(net, gen=np.array([7, 3], dtype=np.uint64))
+    poly = I.make_custom(kind=I.POLY_LATTICE, m=2, s=1, t=1, w=[0], seed=1, b=3)
+    poly = dataclasses.replace(poly, gen=np.array([5], dtype=np.uint64))
+    vn, vp = O.point_values(net, 0, 0), O.point_values(poly, 0, 0)
+    for k, cn, cp in rows:
+        assert vn[k] == cn / 9 and vp[k] == cp / 9
+
+
+B_KINDS = [I.LATTICE, I.POLY_LATTICE, I.DIGITAL_NET]
+
+
+@pytest.mark.parametrize("b,m", BASES)
+@pytest.mark.parametrize("kind", B_KINDS)
+@pytest.mark.parametrize("rand,mp", [(I.NO_SHIFT, I.MAP_ID), (I.RANDOM_SHIFT, I.MAP_CENTER),
+                                     (I.DIGITAL_SHIFT, I.MAP_ID), (I.DIGITAL_SHIFT, I.MAP_TENT)])
+def test_base_b_all_kinds_match_unreduced_definition(oracle_lib, b, m, kind, rand, mp):
+    """Sec. 1.1, 1.3 and 3 over F_b: lattices, polynomial lattices (nu of
+    k(x) x^{w_j} g'_j(x) / x^m) and lower-triangular nets (eq. def:digital with
+    the reduced matrices), unshifted, randomly shifted or digitally shifted mod
+    b, reproduce the brute-force unreduced point sets bit for bit, indexed by
+    k mod n_j."""
+    O = oracle_lib
+    wl = small_b(b, m, rand, mp, kind=kind, s=9)
+    for r in range(wl.R):
+        X = brute.point_matrix(wl, r)
+        for j in range(wl.s):
+            vals = O.point_values(wl, r, j)
+            np.testing.assert_array_equal(vals[np.arange(wl.N) % len(vals)], X[:, j])
+
+
+@pytest.mark.parametrize("b,m", BASES)
+@pytest.mark.parametrize("kind", [I.POLY_LATTICE, I.DIGITAL_NET])
+def test_base_b_alg1_equals_dense_nets_and_polys(oracle_lib, b, m, kind):
+    """Algorithm 1 on base-b polynomial lattices and nets (digitally shifted,
+    and through Phi^-1) agrees with the dense product of the unreduced points."""
+    O = oracle_lib
+    for mp in (I.MAP_ID, I.MAP_INVNORM):
+        wl = small_b(b, m, I.DIGITAL_SHIFT, mp, kind=kind, s=15, t=9)
+        for r in range(wl.R):
+            Yd = O.dense_matvec(O.point_matrix_unreduced(wl, r), wl.A.astype(np.float64))
+            assert np.linalg.norm(O.reduced_matvec(wl, r) - Yd) <= 1e-13 * np.linalg.norm(Yd)
+
+
+@pytest.mark.parametrize("b,m", BASES)
+@pytest.mark.parametrize("kind", B_KINDS)
+def test_base_b_digital_shift_linear_integrand_exact(oracle_lib, b, m, kind):
+    """eq. QMC-rule with g = h = id under a digital shift mod b: the first e
+    digits of the n = b^e values run over all of F_b^e (the leading e x e block
+    is invertible), so they average to (n-1)/(2n); the digits past e are the
+    shift's, (delta mod b^{K-e}) / b^K, plus the midpoint b^-K / 2."""
+    O = oracle_lib
+    wl = small_b(b, m, I.DIGITAL_SHIFT, kind=kind, s=25, t=6, R=3, g=I.G_ID, h=I.H_ID)
+    K = I.shift_digits(b)
+    Q, _ = O.estimate(wl)
+    A = wl.A.astype(np.float64)
+    for r in range(wl.R):
+        mu = []
+        for j in range(wl.s):
+            e = wl.m - min(int(wl.w[j]), wl.m)
+            n = b ** e
+            tail = int(wl.dshift[r, j]) % b ** (K - e)
+            mu.append((n - 1) / (2 * n) + tail / b ** K + 0.5 / b ** K)
+        ref = float(np.mean(np.array(mu) @ A))
+        assert abs(Q[r] - ref) <= 1e-13 * max(1.0, abs(ref))
+
+
+def test_base_b_net_not_periodic_is_refused(oracle_lib):
+    """A base-3 net whose reduced matrix has a nonzero entry in a column past
+    n_j is not periodic; the oracle takes base b > 2 nets only when periodic."""
+    import dataclasses
+    O = oracle_lib
+    wl = I.make_custom(kind=I.DIGITAL_NET, m=3, s=2, t=2, w=[0, 1], seed=2, b=3)
+    assert O.net_is_periodic(wl)
+    gen = wl.gen.copy()
+    gen[1 * 3 + 2] = np.uint64(1)  # C^{(2)}_{1,3} = 1: row 1 <= e = 2 in column 3 > e
+    bad = dataclasses.replace(wl, gen=gen)
+    assert not O.net_is_periodic(bad)
+    with pytest.raises(AssertionError):
+        O.point_values(bad, 0, 0)
