@@ -18,9 +18,9 @@
  *
  * Conventions for every call:
  *   - Indices are 0-based: coordinate j = 0..s-1 is the paper's j+1.
- *   - b is a prime.  Every kind is supported for b = 2 with 1 <= m <= 24;
- *     lattices and reduced Monte Carlo also in a prime base b > 2 (without
- *     the digital shift), with N = b^m <= 2^24 (QMC_EUNSUPPORTED otherwise).
+ *   - b is a prime, 1 <= m <= 24 and N = b^m <= 2^24 (QMC_EUNSUPPORTED
+ *     otherwise).  In a base b > 2 every kind is supported except nets that
+ *     are not periodic after reduction (Algorithm 4 is built for b = 2).
  *   - Matrices are row-major FP32 with an explicit leading dimension.
  *   - "device" pointers are HIP device memory on the device that was current
  *     when the point set was created; "host" pointers are ordinary memory.
@@ -96,6 +96,10 @@ typedef enum { QMC_H_ID = 0, QMC_H_CALL = 1 /* max(0, u - K) */ } qmc_h;
  *   gen    lattice: [s] z'_j below b^{m-w_j} and not divisible by b (odd for
  *                 b = 2), or z'_j = 1 when w_j >= m (the set U_{b^{m-w}} of
  *                 Section 1.3); the generating vector is z_j = b^{w_j} z'_j.
+ *          In a base b > 2, polynomials and matrix columns below are given by
+ *          their base-b digits instead of bits: g'_j as the integer g'_j(b)
+ *          (digit i = coefficient of x^i, nonzero constant term, degree
+ *          < m - w_j), and column word [j*m + q-1] = sum_p C_{p,q} b^{p-1}.
  *          poly lattice: [s] bit masks of g'_j in F_2[x] (bit i = coefficient
  *                 of x^i), g'_j(0) = 1, deg g'_j < m - w_j (g'_j = 1 when
  *                 w_j >= m); the generating polynomial is x^{w_j} g'_j.
@@ -110,8 +114,12 @@ typedef enum { QMC_H_ID = 0, QMC_H_CALL = 1 /* max(0, u - K) */ } qmc_h;
  *                 otherwise (Sobol'-type, upper-triangular C^{(j)}) every
  *                 product uses Algorithm 4 (Section 3).
  *          reduced Monte Carlo (QMC_IID): ignored (may be NULL).
- *   rand, R, shift [R*s] in [0,1) (QMC_RANDOM_SHIFT) or dshift [R*s] < 2^52
- *                 (QMC_DIGITAL_SHIFT): R independent randomisations, all
+ *   rand, R, shift [R*s] in [0,1) (QMC_RANDOM_SHIFT) or dshift [R*s] < b^K
+ *                 (QMC_DIGITAL_SHIFT; K the largest with b^K <= 2^52, so 2^52
+ *                 for b = 2): the K base-b digits of dshift (most significant
+ *                 first) are added digit by digit mod b (XOR for b = 2) to
+ *                 the point's first K digits and the rest is replaced by its
+ *                 midpoint, x = (U + 1/2) / b^K.  R independent randomisations, all
  *                 evaluated by one call.  With QMC_NO_SHIFT, R must be 1,
  *                 except for QMC_IID, where rand must be QMC_NO_SHIFT and R
  *                 counts independent replicates.
@@ -151,12 +159,12 @@ typedef struct qmc_points_s *qmc_points;
  * decreasing, a generator outside its allowed set, shift outside [0,1) or
  * >= 2^52, R < 1, INVNORM without a shift, QMC_IID with a shift, without
  * samples or with a sample outside [0,1) ((0,1) under INVNORM);
- * EUNSUPPORTED: m outside [1, 24], b^m > 2^24, b > 2 with a digital net, a
- * polynomial lattice or the digital shift), plans the levels and uploads
- * generators, shifts and samples.  A base b > 2 is evaluated like Algorithm 4:
- * the n_j values of every coordinate (Section 1.3: c / b^e, one correctly
- * rounded FP64 division before shift and map; Section 4 for samples) are
- * tabulated, and point k reads value k mod n_j.
+ * EUNSUPPORTED: m outside [1, 24], b^m > 2^24, a net in base b > 2 that is
+ * not periodic after reduction), plans the levels and uploads generators,
+ * shifts and samples.  A base b > 2 is evaluated like Algorithm 4: the n_j
+ * values of every coordinate (c / b^e, one correctly rounded FP64 division
+ * before shift and map; Section 4 for samples) are tabulated, and point k
+ * reads value k mod n_j.
  * Synchronous.  *out owns device memory; release with qmc_points_free.
  */
 qmc_status qmc_points_init(qmc_points *out, const qmc_point_spec *spec);

@@ -351,8 +351,6 @@ qmc_status qmc_points_init(qmc_points *out, const qmc_point_spec *sp) {
   if (Nb > kMaxPoints) return fail(QMC_EUNSUPPORTED, "N = %d^%d exceeds %lld points", b, sp->m, (long long)kMaxPoints);
   if (sp->s < 1) return fail(QMC_EINVAL, "s = %d must be >= 1", sp->s);
   if (sp->kind < QMC_LATTICE || sp->kind > QMC_IID) return fail(QMC_EINVAL, "unknown kind %d", sp->kind);
-  if (b != 2 && sp->kind != QMC_LATTICE && sp->kind != QMC_IID)
-    return fail(QMC_EUNSUPPORTED, "digital nets and polynomial lattices are built for b = 2 only (b = %d)", b);
   const bool iid = sp->kind == QMC_IID;
   if (!sp->w || (!sp->gen && !iid)) return fail(QMC_EINVAL, "w or gen is null");
   const int m = sp->m, s = sp->s;
@@ -367,15 +365,32 @@ qmc_status qmc_points_init(qmc_points *out, const qmc_point_spec *sp) {
   if (sp->kind == QMC_DIGITAL_NET) {
     gen.resize((size_t)s * m);
     for (int j = 0; j < s; ++j) {
-      const uint64_t mask = (uint64_t(1) << nbv[j]) - 1;
+      uint64_t ne = 1;  // b^{e_j}
+      for (int i = 0; i < nbv[j]; ++i) ne *= (uint64_t)b;
       for (int q = 0; q < m; ++q) {
         const uint64_t wd = sp->gen[(size_t)j * m + q];
-        if (wd >> m) return fail(QMC_EINVAL, "net column word (j=%d, q=%d) has bits beyond row m", j, q + 1);
-        // a column past n_j with bits in the first n_j rows: the reduced net
-        // depends on every digit of k and its products use Algorithm 4
-        if (q >= nbv[j] && (wd & mask)) nonperiodic = true;
+        // base-b digit p-1 of the word is C_{p,q}: the word is below b^m
+        if (wd >= (uint64_t)Nb) return fail(QMC_EINVAL, "net column word (j=%d, q=%d) has digits beyond row m", j, q + 1);
+        // a column past n_j with nonzero digits in the first n_j rows: the
+        // reduced net depends on every digit of k and its products use
+        // Algorithm 4 (base 2)
+        if (q >= nbv[j] && (b == 2 ? (wd & (ne - 1)) : wd % ne) != 0) nonperiodic = true;
         gen[(size_t)j * m + q] = (uint32_t)wd;
       }
+    }
+    if (nonperiodic && b != 2)
+      return fail(QMC_EUNSUPPORTED, "a net in base %d must be periodic after reduction (Algorithm 4 is built for b = 2)", b);
+  } else if (sp->kind == QMC_POLY_LATTICE && b != 2) {
+    gen.resize(s);
+    for (int j = 0; j < s; ++j) {
+      const uint64_t g = sp->gen[j];
+      uint64_t ne = 1;
+      for (int i = 0; i < nbv[j]; ++i) ne *= (uint64_t)b;
+      // g'_j(b): digits are the coefficients, degree < e_j, nonzero constant term
+      if (nbv[j] == 0 ? g != 1 : (g >= ne || g % (uint64_t)b == 0))
+        return fail(QMC_EINVAL, "polynomial %llu of coordinate %d is not a unit of degree < %d over F_%d",
+                    (unsigned long long)g, j, nbv[j], b);
+      gen[j] = (uint32_t)g;
     }
   } else if (iid) {
     gen.assign(s, 0u);  // reduced Monte Carlo draws no generators
@@ -396,8 +411,6 @@ qmc_status qmc_points_init(qmc_points *out, const qmc_point_spec *sp) {
     }
   }
   if (sp->rand < QMC_NO_SHIFT || sp->rand > QMC_DIGITAL_SHIFT) return fail(QMC_EINVAL, "unknown randomisation %d", sp->rand);
-  if (b != 2 && sp->rand == QMC_DIGITAL_SHIFT)
-    return fail(QMC_EUNSUPPORTED, "the digital shift is built for b = 2 only (b = %d)", b);
   if (sp->R < 1) return fail(QMC_EINVAL, "R = %d must be >= 1", sp->R);
   if (iid && sp->rand != QMC_NO_SHIFT)
     return fail(QMC_EINVAL, "reduced Monte Carlo takes no shift (R counts independent replicates)");
@@ -410,8 +423,10 @@ qmc_status qmc_points_init(qmc_points *out, const qmc_point_spec *sp) {
   }
   if (sp->rand == QMC_DIGITAL_SHIFT) {
     if (!sp->dshift) return fail(QMC_EINVAL, "dshift is null");
+    uint64_t bK = 1;  // b^K, K digits of the shift: the largest with b^K <= 2^52
+    while (bK <= (uint64_t(1) << 52) / (uint64_t)b) bK *= (uint64_t)b;
     for (int64_t i = 0; i < (int64_t)sp->R * s; ++i)
-      if (sp->dshift[i] >> 52) return fail(QMC_EINVAL, "dshift[%lld] >= 2^52", (long long)i);
+      if (sp->dshift[i] >= bK) return fail(QMC_EINVAL, "dshift[%lld] >= %llu (b^K)", (long long)i, (unsigned long long)bK);
   }
   if (sp->map < QMC_MAP_ID || sp->map > QMC_MAP_TENT) return fail(QMC_EINVAL, "unknown map %d", sp->map);
   if (sp->map == QMC_MAP_INVNORM && sp->rand == QMC_NO_SHIFT && !iid)

@@ -22,12 +22,23 @@ namespace qmc {
 // The point-set constants the value computation needs.
 struct PointConsts {
   int32_t m, s, kind, rand, map, b;
+  int32_t kdig;         // base b > 2, digital shift: K digits, b^K <= 2^52
+  double bK;            // b^K (exact)
   int32_t by_output;    // rho is already the integer c of the value c / 2^nb (value tables of nets)
   int32_t nonperiodic;  // a reduced net that depends on every input digit
 };
 
 static PointConsts consts_of(const Geometry &G) {
-  return PointConsts{G.m, G.s, G.kind, G.rand, G.map, G.b, 0, G.nonperiodic};
+  PointConsts pc{G.m, G.s, G.kind, G.rand, G.map, G.b, 0, 1.0, 0, G.nonperiodic};
+  if (G.b != 2) {
+    uint64_t v = 1;
+    while (v <= (uint64_t(1) << 52) / (uint64_t)G.b) {
+      v *= (uint64_t)G.b;
+      ++pc.kdig;
+    }
+    pc.bK = (double)v;
+  }
+  return pc;
 }
 
 __host__ __device__ __forceinline__ uint64_t ipow_u64(uint32_t b, int e) {
@@ -36,18 +47,69 @@ __host__ __device__ __forceinline__ uint64_t ipow_u64(uint32_t b, int e) {
   return r;
 }
 
+// Base b > 2 (every point set periodic in k mod n_j, n_j = b^nb): the integer
+// c of c / n_j at residue rho.  Lattice rho z' mod n_j; polynomial lattice
+// the digits of rho(x) g'_j(x) mod (b, x^nb) (coefficient i = digit i);
+// net the output digits y_p = sum_q C_{p,q} rho_q mod b (p <= nb, column word
+// q holds C_{p,q} as digit p-1), read most significant first.
+// (out of line: the digit arrays live in scratch; lattices take the inline
+// path in value_int)
+__device__ __noinline__ uint32_t value_int_b(const PointConsts &G, const uint32_t *__restrict__ gen, int j,
+                                             uint32_t rho, int nb) {
+  const uint32_t b = (uint32_t)G.b;
+  uint32_t rd[32], y[32];  // nb <= 24 (b^nb <= 2^24)
+  for (int i = 0; i < nb; ++i) {
+    rd[i] = rho % b;
+    rho /= b;
+    y[i] = 0;
+  }
+  if (G.kind == QMC_POLY_LATTICE) {
+    uint32_t g = gen[j], gd[32];
+    for (int i = 0; i < nb; ++i) {
+      gd[i] = g % b;
+      g /= b;
+    }
+    uint32_t c = 0;
+    for (int i = nb - 1; i >= 0; --i) {  // coefficient i of the product is digit i
+      uint32_t acc = 0;
+      for (int k = 0; k <= i; ++k) acc += rd[k] * gd[i - k];
+      c = c * b + acc % b;
+    }
+    return c;
+  }
+  const uint32_t *col = gen + (size_t)j * G.m;
+  for (int q = 0; q < nb; ++q) {  // digits of rho past nb are zero
+    if (!rd[q]) continue;
+    uint32_t wd = col[q];
+    for (int p = 0; p < nb; ++p) {
+      y[p] += (wd % b) * rd[q];
+      wd /= b;
+    }
+  }
+  uint32_t c = 0;
+  for (int p = 0; p < nb; ++p) c = c * b + y[p] % b;
+  return c;
+}
+
 // The integer c of the value c / 2^nb of coordinate j at input index rho:
 // lattice rho z' mod 2^nb; polynomial lattice the carry-less product; net the
 // XOR of the generating-matrix columns selected by the digits of rho (all of
 // them: for a net that repeats with period n_j the columns past nb carry no
 // bits in the first nb rows), truncated to nb rows and read most significant
 // digit first.
+// VB: the class of point sets a kernel serves, so that each kernel holds only
+// its own code (the digit arithmetic of value_int_b needs scratch memory, which
+// costs every launch of a kernel that contains it):
+//   0  base 2;  1  base b > 2, lattices (and reduced Monte Carlo);
+//   2  base b > 2, polynomial lattices and nets.
+template <int VB>
 __device__ __forceinline__ uint32_t value_int(const PointConsts &G, const uint32_t *__restrict__ gen,
                                               int j, uint32_t rho, int nb) {
   if (nb == 0) return 0u;
+  if constexpr (VB == 1) return (uint32_t)(((uint64_t)rho * gen[j]) % ipow_u64(G.b, nb));
+  if constexpr (VB == 2) return value_int_b(G, gen, j, rho, nb);
   const uint32_t mask = (nb >= 32) ? 0xffffffffu : ((1u << nb) - 1u);
   if (G.by_output) return rho & mask;
-  if (G.kind == QMC_LATTICE && G.b != 2) return (uint32_t)(((uint64_t)rho * gen[j]) % ipow_u64(G.b, nb));
   if (G.kind == QMC_LATTICE) return (rho * gen[j]) & mask;
   if (G.kind == QMC_POLY_LATTICE) {
     const uint32_t g = gen[j];
@@ -111,7 +173,7 @@ __device__ __forceinline__ double ppnd16(double p) {
   return q < 0.0 ? -v : v;
 }
 
-template <bool INVNORM>
+template <bool INVNORM, int VB = 0>
 __device__ __forceinline__ double value_f64(const PointConsts &G, const DevSpec &D, int r, int j,
                                             uint32_t rho, int nb) {
   double x;
@@ -119,14 +181,33 @@ __device__ __forceinline__ double value_f64(const PointConsts &G, const DevSpec 
     // reduced Monte Carlo (Section 4, eq. randpts): the distinct values of
     // coordinate j are its own i.i.d. samples, point k taking sample k mod n_j
     x = D.samples[(size_t)r * D.sample_total + D.soff[j] + rho];
-  } else if (G.rand == QMC_DIGITAL_SHIFT) {
-    const uint32_t c = value_int(G, D.gen, j, rho, nb);
+  } else if (VB == 0 && G.rand == QMC_DIGITAL_SHIFT) {
+    const uint32_t c = value_int<0>(G, D.gen, j, rho, nb);
     const uint64_t U = ((uint64_t)c << (52 - nb)) ^ D.dshift[(size_t)r * G.s + j];
     x = (double)(2 * U + 1) * 0x1p-53;  // exact
+  } else if (G.rand == QMC_DIGITAL_SHIFT) {
+    // base b: digits p = 1..K of x are those of c (p <= nb) plus those of
+    // delta (most significant first), mod b; then the midpoint of the rest
+    const uint64_t b = (uint64_t)G.b;
+    const uint32_t c = value_int<VB>(G, D.gen, j, rho, nb);
+    uint64_t dl = D.dshift[(size_t)r * G.s + j], cc = c, U = 0, pw = 1;
+    for (int i = 0; i < G.kdig; ++i) {  // digit p = K - i
+      const int p = G.kdig - i;
+      uint64_t yp = 0;
+      if (p <= nb) {  // digit p of c / b^nb is digit nb - p of c
+        uint64_t t = cc;
+        for (int k = 0; k < nb - p; ++k) t /= b;
+        yp = t % b;
+      }
+      U += ((yp + dl % b) % b) * pw;
+      dl /= b;
+      pw *= b;
+    }
+    x = __ddiv_rn((double)U + 0.5, G.bK);  // U + 1/2 exact (U < 2^52); one rounding
   } else {
-    const uint32_t c = value_int(G, D.gen, j, rho, nb);
-    x = G.b == 2 ? (double)c * __builtin_ldexp(1.0, -nb)  // exact
-                 : __ddiv_rn((double)c, (double)ipow_u64(G.b, nb));
+    const uint32_t c = value_int<VB>(G, D.gen, j, rho, nb);
+    if constexpr (VB != 0) x = __ddiv_rn((double)c, (double)ipow_u64(G.b, nb));
+    else x = (double)c * __builtin_ldexp(1.0, -nb);  // exact
     if (G.rand == QMC_RANDOM_SHIFT) {
       x = __dadd_rn(x, D.shift[(size_t)r * G.s + j]);
       if (x >= 1.0) x = __dsub_rn(x, 1.0);
@@ -212,14 +293,14 @@ __global__ __launch_bounds__(256) void tables_kernel(TabArgs ta, DevSpec D, int 
   }
 }
 
-template <bool INVNORM>
+template <bool INVNORM, int VB>
 __global__ void values_kernel(PointConsts G, DevSpec D, int r, int j, int nb, double *__restrict__ out) {
   const uint32_t n = (uint32_t)ipow_u64(G.b, nb);
   for (uint32_t rho = blockIdx.x * blockDim.x + threadIdx.x; rho < n; rho += gridDim.x * blockDim.x)
-    out[rho] = value_f64<INVNORM>(G, D, r, j, rho, nb);
+    out[rho] = value_f64<INVNORM, VB>(G, D, r, j, rho, nb);
 }
 
-template <bool INVNORM>
+template <bool INVNORM, int VB>
 __global__ void point_matrix_kernel(PointConsts G, DevSpec D, int r, float *__restrict__ X, int64_t ldx) {
   const int64_t total = (int64_t)ipow_u64(G.b, G.m) * G.s;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
@@ -231,9 +312,25 @@ __global__ void point_matrix_kernel(PointConsts G, DevSpec D, int r, float *__re
     const uint32_t rho = G.nonperiodic ? (uint32_t)k
                          : G.b == 2    ? (uint32_t)(k & ((int64_t(1) << nb) - 1))
                                        : (uint32_t)(k % (int64_t)ipow_u64(G.b, nb));
-    X[k * ldx + j] = (float)value_f64<INVNORM>(G, D, r, j, rho, nb);
+    X[k * ldx + j] = (float)value_f64<INVNORM, VB>(G, D, r, j, rho, nb);
   }
 }
+
+// The kernel instance for a point set: inverse-normal map or not, and its
+// value class VB (see value_int).
+static int value_class(const Geometry &G) {
+  if (G.b == 2) return 0;
+  return G.kind == QMC_POLY_LATTICE || G.kind == QMC_DIGITAL_NET ? 2 : 1;
+}
+#define QMC_DISPATCH_VB(G, LAUNCH)                         \
+  do {                                                     \
+    const bool inv_ = (G).map == QMC_MAP_INVNORM;          \
+    switch (value_class(G)) {                              \
+      case 0: if (inv_) LAUNCH(true, 0); else LAUNCH(false, 0); break; \
+      case 1: if (inv_) LAUNCH(true, 1); else LAUNCH(false, 1); break; \
+      default: if (inv_) LAUNCH(true, 2); else LAUNCH(false, 2); break; \
+    }                                                      \
+  } while (0)
 
 static int grid_for(int64_t work, int threads) {
   int64_t g = ceil_div(work, threads);
@@ -288,10 +385,9 @@ hipError_t launch_point_values(const Geometry &G, const DevSpec &D, int r, int j
   const dim3 grid(grid_for((int64_t)ipow_u64(G.b, nb), 256));
   PointConsts pc = consts_of(G);
   pc.by_output = G.nonperiodic;  // such a net's values are listed by their output digits
-  if (G.map == QMC_MAP_INVNORM)
-    hipLaunchKernelGGL(values_kernel<true>, grid, dim3(256), 0, st, pc, D, r, j, nb, out);
-  else
-    hipLaunchKernelGGL(values_kernel<false>, grid, dim3(256), 0, st, pc, D, r, j, nb, out);
+#define QMC_VALUES(I, V) hipLaunchKernelGGL((values_kernel<I, V>), grid, dim3(256), 0, st, pc, D, r, j, nb, out)
+  QMC_DISPATCH_VB(G, QMC_VALUES);
+#undef QMC_VALUES
   return hipGetLastError();
 }
 
@@ -299,10 +395,10 @@ hipError_t launch_point_matrix(const Geometry &G, const DevSpec &D, int r, float
                                hipStream_t st) {
   LaunchTimer tm("points", st);
   const dim3 grid(grid_for(G.N * G.s, 256));
-  if (G.map == QMC_MAP_INVNORM)
-    hipLaunchKernelGGL(point_matrix_kernel<true>, grid, dim3(256), 0, st, consts_of(G), D, r, X, ldx);
-  else
-    hipLaunchKernelGGL(point_matrix_kernel<false>, grid, dim3(256), 0, st, consts_of(G), D, r, X, ldx);
+  const PointConsts pc = consts_of(G);
+#define QMC_PMAT(I, V) hipLaunchKernelGGL((point_matrix_kernel<I, V>), grid, dim3(256), 0, st, pc, D, r, X, ldx)
+  QMC_DISPATCH_VB(G, QMC_PMAT);
+#undef QMC_PMAT
   return hipGetLastError();
 }
 
@@ -312,7 +408,7 @@ hipError_t launch_point_matrix(const Geometry &G, const DevSpec &D, int r, float
 // soff.  Nets (digit order): rho is the digit word y, stored at aoff_j + y,
 // the value that of the output integer bitreverse(y).  Base b > 2: rho is the
 // residue, stored at aoff_j + rho and aoff_j + rho + n_j.
-template <bool INVNORM>
+template <bool INVNORM, int VB>
 __global__ __launch_bounds__(256) void outvals_kernel(PointConsts G, DevSpec D, int r0, int64_t stride,
                                                       float *__restrict__ out) {
   const int rl = blockIdx.y;
@@ -326,12 +422,12 @@ __global__ __launch_bounds__(256) void outvals_kernel(PointConsts G, DevSpec D, 
     const int nb = D.nbj[lo];
     const uint32_t y = (uint32_t)(e - D.soff[lo]);
     float *o = out + (int64_t)rl * stride + D.aoff[lo];
-    if (G.b == 2) {
+    if constexpr (VB == 0) {
       const uint32_t c = nb == 0 ? 0u : __builtin_bitreverse32(y) >> (32 - nb);
-      o[y] = (float)value_f64<INVNORM>(G, D, r0 + rl, lo, c, nb);
+      o[y] = (float)value_f64<INVNORM, 0>(G, D, r0 + rl, lo, c, nb);
     } else {
       const int64_t n = (lo + 1 < G.s ? D.soff[lo + 1] : total) - D.soff[lo];
-      const float v = (float)value_f64<INVNORM>(G, D, r0 + rl, lo, y, nb);
+      const float v = (float)value_f64<INVNORM, VB>(G, D, r0 + rl, lo, y, nb);
       o[y] = v;
       o[y + n] = v;
     }
@@ -344,10 +440,10 @@ hipError_t launch_output_tables(const Geometry &G, const DevSpec &D, int r0, int
   PointConsts pc = consts_of(G);
   pc.by_output = G.nonperiodic;  // nets: the value of an output integer
   const dim3 grid(grid_for(D.sample_total, 256), nr);
-  if (G.map == QMC_MAP_INVNORM)
-    hipLaunchKernelGGL(outvals_kernel<true>, grid, dim3(256), 0, st, pc, D, r0, G.gather_total, out);
-  else
-    hipLaunchKernelGGL(outvals_kernel<false>, grid, dim3(256), 0, st, pc, D, r0, G.gather_total, out);
+#define QMC_OUTVALS(I, V) \
+  hipLaunchKernelGGL((outvals_kernel<I, V>), grid, dim3(256), 0, st, pc, D, r0, G.gather_total, out)
+  QMC_DISPATCH_VB(G, QMC_OUTVALS);
+#undef QMC_OUTVALS
   return hipGetLastError();
 }
 

@@ -109,11 +109,16 @@ def lat3(**kw):
 
 
 BASE_CASES = [
-    ("b = 3 digital net", lambda wl: _spec(wl, kind=I.DIGITAL_NET,
-                                           gen=np.ones(10 * 5, dtype=np.uint64)), 2),
-    ("b = 3 polynomial lattice", lambda wl: _spec(wl, kind=I.POLY_LATTICE), 2),
+    ("b = 3 net not periodic", lambda wl: _spec(wl, kind=I.DIGITAL_NET,
+                                                gen=np.ones(10 * 5, dtype=np.uint64)), 2),
+    ("b = 3 polynomial lattice", lambda wl: _spec(wl, kind=I.POLY_LATTICE), 4),
+    ("b = 3 polynomial without constant term", lambda wl: _spec(wl, kind=I.POLY_LATTICE,
+                                                                gen=np.r_[[3], wl.gen[1:]]), 1),
     ("b = 3 digital shift", lambda wl: _spec(wl, rand=I.DIGITAL_SHIFT, shift=None,
-                                             dshift=np.zeros((2, 10), dtype=np.uint64)), 2),
+                                             dshift=np.zeros((2, 10), dtype=np.uint64)), 4),
+    ("b = 3 digital shift >= b^K", lambda wl: _spec(wl, rand=I.DIGITAL_SHIFT, shift=None,
+                                                    dshift=np.full((2, 10), 3 ** I.shift_digits(3),
+                                                                   dtype=np.uint64)), 1),
     ("b^m above 2^24", lambda wl: _spec(wl, m=16), 2),
     ("generator divisible by b", lambda wl: _spec(wl, gen=np.r_[[3], wl.gen[1:]]), 1),
     ("generator not below b^e", lambda wl: _spec(wl, gen=np.r_[[3 ** 5 + 1], wl.gen[1:]]), 1),
@@ -123,8 +128,9 @@ BASE_CASES = [
 
 @pytest.mark.parametrize("name,make,code", BASE_CASES, ids=[c[0] for c in BASE_CASES])
 def test_base_b_points_init_validation(name, make, code):
-    """A prime base b > 2 (Section 1.3): lattices and reduced Monte Carlo only,
-    N = b^m up to 2^24, generators z'_j units modulo b^{m-w_j} (code 4: the
+    """A prime base b > 2 (Sections 1.1, 1.3, 3): N = b^m up to 2^24, lattice
+    generators units modulo b^{m-w_j}, polynomials with a nonzero constant
+    term, nets periodic after reduction, digital shifts below b^K (code 4: the
     spec is valid and the call reaches the device check, no GPU here)."""
     import torch
     if code == 4 and torch.cuda.is_available():

@@ -536,6 +536,50 @@ def test_base_b_reduced_monte_carlo(mp):
     assert np.all(np.abs(Q - Qo) <= Q_TOL * np.abs(Qo)), (Q, Qo)
 
 
+@pytest.mark.parametrize("b,m", [(3, 6), (5, 4)])
+@pytest.mark.parametrize("kind", [I.POLY_LATTICE, I.DIGITAL_NET])
+@pytest.mark.parametrize("rand,mp", [(I.NO_SHIFT, I.MAP_ID), (I.RANDOM_SHIFT, I.MAP_TENT),
+                                     (I.DIGITAL_SHIFT, I.MAP_ID), (I.DIGITAL_SHIFT, I.MAP_INVNORM)])
+def test_base_b_nets_and_polys_tables_bit_exact(b, m, kind, rand, mp):
+    """Polynomial lattices and nets over F_b (Sections 1.1, 3), unshifted,
+    randomly shifted or digitally shifted mod b: the n_j values equal the
+    oracle's bit for bit (the inverse-normal map to 1e-14)."""
+    from oracle import oracle as O
+    torch_cuda()
+    wl = lat_b(b, m, rand, mp, s=20, kind=kind)
+    pts = q.Points.from_workload(wl)
+    for r in range(wl.R):
+        for j in range(wl.s):
+            got, ref = q.point_values(pts, r, j).cpu().numpy(), O.point_values(wl, r, j)
+            if mp == I.MAP_INVNORM:
+                np.testing.assert_allclose(got, ref, rtol=1e-14, atol=0)
+            else:
+                np.testing.assert_array_equal(got, ref)
+
+
+@pytest.mark.parametrize("kind", [I.POLY_LATTICE, I.DIGITAL_NET])
+@pytest.mark.parametrize("prec", [I.FP32, I.SPLIT_BF16X3])
+def test_base_b_nets_and_polys_matvec_and_estimate(kind, prec):
+    """Digitally shifted base-3 polynomial lattice and net through Phi^-1: every
+    product element within the bound (point matrix equal to the FP32 rounding
+    of the unreduced points), and a call-type estimate within 1e-6."""
+    from oracle import oracle as O
+    torch = torch_cuda()
+    wl = lat_b(3, 7, I.DIGITAL_SHIFT, I.MAP_INVNORM, s=45, t=100, kind=kind, g=I.G_EXP, h=I.H_CALL, c=0.2,
+               K=1.0)
+    pts = q.Points.from_workload(wl)
+    np.testing.assert_array_equal(q.point_matrix(pts, 1).cpu().numpy(),
+                                  O.point_matrix_unreduced(wl, 1).astype(np.float32))
+    A = to_dev(wl.A, torch)
+    for r in range(wl.R):
+        Y = q.reduced_matvec(pts, A, r=r, prec=prec).cpu().numpy()
+        _check_Y(wl, Y, r, prec)
+    if prec == I.FP32:
+        Q = q.estimate(pts, A, q.Integrand_.of(wl)).cpu().numpy()
+        Qo, _ = O.estimate(wl)
+        assert np.all(np.abs(Q - Qo) <= Q_TOL * np.maximum(np.abs(Qo), 1e-3)), (Q, Qo)
+
+
 def test_base_b_gradient_is_unsupported():
     torch = torch_cuda()
     wl = lat_b(3, 6)
