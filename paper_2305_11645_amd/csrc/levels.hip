@@ -187,7 +187,8 @@ __global__ __launch_bounds__(256) void levels_gemm(GemmArgs g, const float *__re
     if (row < P.M && col < P.N) {
       float out = acc[v];
       if (PREC != QMC_FP32) out += acc2[v];
-      Cb[(int64_t)row * g.ldc + col] = g.oscale * out;
+      // streamed past the L2 (read next by another kernel, on other XCDs)
+      __builtin_nontemporal_store(g.oscale * out, &Cb[(int64_t)row * g.ldc + col]);
     }
   }
 }
