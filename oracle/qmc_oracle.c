@@ -41,7 +41,8 @@
  *     exp(c y)} and h in {u, max(0, u - K)}; h'(K) is taken as 0;
  *   - the gradient dQ/dA is the plain chain rule; its reduced form (fold of
  *     the point-wise sensitivities over residue classes, then the distinct
- *     values) is the transpose of Algorithm 1.
+ *     values) is the transpose of Algorithm 1, or of Algorithm 4 for a net
+ *     that is not periodic (sums over the points sharing a value).
  *
  * Build: gcc -O2 -fopenmp -ffp-contract=off -shared -fPIC (no FMA contraction,
  * so every table value is one IEEE operation sequence).
@@ -612,32 +613,60 @@ int qo_estimate(const qo_spec *sp, const double *A, int t, const qo_integrand *f
  * over k folds into residue classes: S_j[rho] = sum_{k = rho mod n_j} G_k,
  * dA_j = sum_rho X_j[rho] S_j[rho].  The fold is done j = 0 .. s-1, each
  * step summing the classes of the previous (finer) one: the transpose of the
- * tiling in Algorithm 1.  Also returns Q.
+ * tiling in Algorithm 1.  A net that is not periodic after reduction takes
+ * the transpose of Algorithm 4 instead (see there).  Also returns Q.
  */
 int qo_estimate_grad(const qo_spec *sp, const double *A, int t, const qo_integrand *f,
                      double *Q, double *dA) {
-    if (!net_is_periodic(sp)) return 2;  /* the fold below needs periodic tables */
     int64_t N = N_of(sp);
     int s = sp->s, tb = block_width(t);
+    const int periodic = net_is_periodic(sp);
     double *P = (double *)malloc(sizeof(double) * (size_t)N * tb);
     double *u = (double *)malloc(sizeof(double) * (size_t)N);
     double *hv = (double *)malloc(sizeof(double) * (size_t)N);
     double *v = (double *)malloc(sizeof(double) * (size_t)N);
-    if (!P || !u || !hv || !v) { free(P); free(u); free(hv); free(v); return 1; }
+    double *S = periodic ? NULL : (double *)malloc(sizeof(double) * (size_t)N * tb);
+    if (!P || !u || !hv || !v || (!periodic && !S)) {
+        free(P); free(u); free(hv); free(v); free(S); return 1;
+    }
     int R = replicates(sp);
     for (int r = 0; r < R; ++r) {
-        if (point_means(sp, r, A, t, f, u, P, NULL)) { free(P); free(u); free(hv); free(v); return 1; }
+        if (point_means(sp, r, A, t, f, u, P, NULL)) { free(P); free(u); free(hv); free(v); free(S); return 1; }
         for (int64_t k = 0; k < N; ++k) hv[k] = h_val(f, u[k]);
         Q[r] = qo_neumaier(hv, N) / (double)N;
         double *dAr = dA + (size_t)r * s * t;
         for (int i0 = 0; i0 < t; i0 += tb) {
             int i1 = i0 + tb < t ? i0 + tb : t, w = i1 - i0;
-            if (qo_alg1(sp, r, A, t, i0, i1, P, NULL)) { free(P); free(u); free(hv); free(v); return 1; }
+            if (reduced_product(sp, r, A, t, i0, i1, P, NULL)) {
+                free(P); free(u); free(hv); free(v); free(S); return 1;
+            }
             /* G in place of Y */
 #pragma omp parallel for schedule(static)
             for (int64_t k = 0; k < N; ++k) {
                 double hk = h_der(f, u[k]) / ((double)N * (double)t);
                 for (int i = 0; i < w; ++i) P[k * w + i] = hk * g_der(f, P[k * w + i]);
+            }
+            if (!periodic) {
+                /* Algorithm 4 transposed (a net that is not periodic, base 2):
+                 * point n contributes to the value X_j[c] with c = floor(y_{n,j} n_j),
+                 * the integer of its reduced output digits, so
+                 * dA_j = sum_c X_j[c] S_j[c],  S_j[c] = sum of G_n over those n */
+                for (int j = 0; j < s; ++j) {
+                    int nb = nbits_of(sp, j);
+                    int64_t nj = (int64_t)1 << nb;
+                    for (int64_t e = 0; e < nj * w; ++e) S[e] = 0.0;
+                    for (int64_t n = 0; n < N; ++n) {
+                        uint64_t c = unreduced_int_over_N(sp, j, (uint64_t)n) >> (sp->m - nb);
+                        for (int i = 0; i < w; ++i) S[c * w + i] = S[c * w + i] + P[n * w + i];
+                    }
+                    qo_output_values(sp, r, j, v);
+                    for (int i = 0; i < w; ++i) {
+                        double acc = 0.0;
+                        for (int64_t c = 0; c < nj; ++c) acc = acc + v[c] * S[c * w + i];
+                        dAr[(size_t)j * t + i0 + i] = acc;
+                    }
+                }
+                continue;
             }
             int64_t rows = N;
             for (int j = 0; j < s; ++j) {
@@ -662,7 +691,7 @@ int qo_estimate_grad(const qo_spec *sp, const double *A, int t, const qo_integra
             }
         }
     }
-    free(P); free(u); free(hv); free(v);
+    free(P); free(u); free(hv); free(v); free(S);
     return 0;
 }
 

@@ -782,3 +782,19 @@ def test_base_b_net_not_periodic_is_refused(oracle_lib):
     assert not O.net_is_periodic(bad)
     with pytest.raises(AssertionError):
         O.point_values(bad, 0, 0)
+
+
+@pytest.mark.parametrize("g,h", [(I.G_COS, I.H_ID), (I.G_EXP, I.H_CALL)])
+def test_alg4_gradient_equals_dense(oracle_lib, g, h):
+    """For a net that is not periodic the oracle's dQ/dA (Algorithm 4
+    transposed: sensitivities summed over the points that share a value) equals
+    X^T G with X built digit by digit by brute force."""
+    O = oracle_lib
+    wl = upper_net(m=7, s=12, t=5, R=2, mp=I.MAP_CENTER, g=g, h=h, K=0.05)
+    wl.c = 0.3
+    assert not O.net_is_periodic(wl)
+    Q, dA = O.estimate_grad(wl)
+    A = wl.A.astype(np.float64)
+    for r in range(wl.R):
+        ref = _dense_grad(wl, A, brute.point_matrix(wl, r), r)
+        assert np.linalg.norm(dA[r] - ref) <= 1e-12 * np.linalg.norm(ref)
