@@ -207,6 +207,71 @@ def bench_matvec(args, wl) -> int:
     return 0
 
 
+def bench_grad(args, wl) -> int:
+    """Q and dQ/dA for every randomisation per step (qmc_estimate_grad): the
+    forward pass, the sensitivities and the adjoint products.  value counts the
+    dense-equivalent flops of the forward and adjoint products, 4 N s t R."""
+    import torch
+
+    import paper_2305_11645_amd as q
+
+    prec = wl.prec if args.prec is None else args.prec
+    f = q.Integrand_.of(wl)
+    pts = q.Points.from_workload(wl)
+    A = torch.from_numpy(wl.A).cuda()
+    ws = pts.workspace(2, wl.t, f, prec)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        return q.estimate_grad(pts, A, f, prec, workspace=ws)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        Q, dA = step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+
+    q.timing.reset()
+    q.timing.enable(True)
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    q.timing.enable(False)
+    kern = {}
+    for name in ("tables", "levels", "leaf", "reduce", "levels_adj", "adjoint", "fold", "combine"):
+        tot, n = q.timing.read(name)
+        if n:
+            kern[name] = {"ms_per_step": tot / args.steps, "launches": n}
+    q.timing.reset()
+    roofline = None
+    if "adjoint" in kern:
+        # the adjoint products: 2 N jlow t R flops over all points, plus
+        # 2 n_split (s - jlow) t R over the folded upper coordinates (base b > 2)
+        L = pts.split_level
+        jlow = wl.s if L < 0 else int(np.sum(np.minimum(wl.w, wl.m) < L))
+        nsplit = wl.b ** (wl.m - L) if L >= 0 else 0
+        mf = 2.0 * wl.t * wl.R * (wl.N * jlow + nsplit * (wl.s - jlow)) * (3 if prec == 1 else 1)
+        peak = MFMA_PEAK_TFLOPS[prec]
+        achieved = mf / (kern["adjoint"]["ms_per_step"] * 1e-3) / 1e12
+        roofline = {"bound": "mfma", "kernel": "alg4_adj_kernel", "achieved": round(achieved, 3), "peak": peak,
+                    "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                    "algorithmic_flops": mf}
+    flops = 4.0 * wl.N * wl.s * wl.t * wl.R
+    out = {"metric": "estimate_grad_dense_equivalent_GFLOPs", "value": round(flops / (ms * 1e-3) / 1e9, 3),
+           "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 5),
+           "higher_is_better": True, "dtype": "f32" if prec == 0 else "bf16x3", "data": "synthetic",
+           "config": {"workload": f"C{args.config}", "N": wl.N, "s": wl.s, "t": wl.t, "R": wl.R, "b": wl.b,
+                      "split_level": pts.split_level},
+           "roofline": roofline, "kernels": kern}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -218,8 +283,9 @@ def main() -> int:
     ap.add_argument("--no-dense", action="store_true")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="after timing, run one plain device copy of this many MiB (counter calibration)")
-    ap.add_argument("--op", choices=("estimate", "matvec"), default="estimate",
-                    help="estimate: Q for every randomisation (default); matvec: Y = X A stored in HBM")
+    ap.add_argument("--op", choices=("estimate", "matvec", "grad"), default="estimate",
+                    help="estimate: Q for every randomisation (default); matvec: Y = X A stored in HBM; "
+                         "grad: Q and dQ/dA")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -235,6 +301,8 @@ def main() -> int:
     wl = I.make_config(args.config)
     if args.op == "matvec":
         return bench_matvec(args, wl)
+    if args.op == "grad":
+        return bench_grad(args, wl)
     prec = wl.prec if args.prec is None else args.prec
     f = q.Integrand_.of(wl)
     pts = q.Points.from_workload(wl)

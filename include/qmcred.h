@@ -231,8 +231,12 @@ qmc_status qmc_estimate(qmc_points p, const float *A, int32_t t, int64_t lda, co
  * sensitivities over the residue classes k mod n_j, then the distinct values),
  * with Y recomputed rather than stored.  dA: device, R x s x t FP32, rows of
  * length t (leading dimension t).  workspace as above (op = 2).
- * QMC_EUNSUPPORTED for a net that is not periodic after reduction and for a
- * base b > 2.
+ * A net that is not periodic after reduction (Algorithm 4) and every base
+ * b > 2 take the transpose of the gathered products instead: the point-wise
+ * sensitivities G (R x N x t FP32, part of the workspace) are formed, then
+ * dA = X^T G on the matrix cores (in base b > 2 the coordinates with
+ * n_j <= b^{m-L'} contract over G summed into the b^{m-L'} residues), the
+ * chunk partials added in FP64 in fixed order.
  */
 qmc_status qmc_estimate_grad(qmc_points p, const float *A, int32_t t, int64_t lda,
                              const qmc_integrand *f, int32_t prec, double *Q, float *dA,

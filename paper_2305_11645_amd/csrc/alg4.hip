@@ -30,6 +30,11 @@
 //   StoreY  Y = X A
 //   Sum     per-workgroup FP64 sum of g(y) over the tile (separable f)
 //   Point   per point, the sum of g(y) over the tile's 256 columns (non-separable h)
+//   Grad    the sensitivities G = gscale h'(u_n) g'(y) stored like Y (h' read per
+//           point, or 1 for a separable f, which also writes the Sum partials)
+//
+// The adjoint dA = X^T G (Algorithm 4 transposed) runs on the same tiles with
+// the roles of points and coordinates swapped (alg4_adj_kernel below).
 #include <algorithm>
 
 #include "qmc_internal.h"
@@ -57,6 +62,9 @@ struct Alg4Args {
   const float *root;     // optional root table added to y: row n mod nsplit
   int64_t ldp, root_stride, nsplit;
   float sigma;           // y' = sigma y (scale of g)
+  float gc;              // Grad: parameter c of exp(c y)
+  double gscale;         // Grad: factor of the sensitivities
+  const float *hd;       // Grad: per-point factor h'(u_n) ([randomisation][N]) or null
 };
 
 // Buffer resource of `bytes` bytes at `base` (raw, stride 0): loads at byte
@@ -280,6 +288,37 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC == QMC
             const int col = colw + 32 * c;
             if (row < a.N && col < a.t) Yr[row * a.ldy + col] = a.sigma * acc[i][c][v];
           }
+    } else if (MODE == kModeGrad) {
+      // G = gscale h'(u_n) g'(y), stored like Y; without a per-point factor
+      // (separable f) also the tile's sum of g, as in the summing mode
+      float *Gr = Y + (int64_t)rl * a.ystride;
+      const float *hk = a.hd ? a.hd + (int64_t)rl * a.N : nullptr;
+      float sl = 0.f;
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int64_t row = n0 + row_of(i, v);
+          const float fac = (hk && row < a.N) ? hk[row] : 1.0f;
+#pragma unroll
+          for (int c = 0; c < 2; ++c) {
+            const int col = colw + 32 * c;
+            const float ys = a.sigma * acc[i][c][v];
+            if (row < a.N && col < a.t) {
+              Gr[row * a.ldy + col] = (float)(a.gscale * (double)(fac * g_der<GF>(ys, a.gc)));
+              sl += g_val<GF>(ys);
+            }
+          }
+        }
+      if (a.hd == nullptr) {
+        double d = (double)sl;
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) d += __shfl_xor(d, o, 64);
+        if (lane == 0) red[w] = d;
+        __syncthreads();
+        if (tid == 0)
+          partial[((int64_t)rl * a.ntiles + tn) * a.tct + ct] = ((red[0] + red[1]) + red[2]) + red[3];
+      }
     } else {
       float gv[2][2][16];
 #pragma unroll
@@ -385,6 +424,244 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC == QMC
   }
 }
 
+// ------------------------------------------------------------------ adjoint
+// dA = X^T G over the points of a pass.  Read as Algorithm 4 transposed, every
+// point adds its sensitivities G_n to the value it selects in each coordinate,
+// and dA_j is the sum over values of X_j[c] times that sum: X^T G with the
+// gathered point matrix, which is what the matrix cores evaluate.  The tiles of
+// the forward pass with the roles of points and coordinates swapped: a
+// workgroup owns 32 MI coordinates x 256 columns of dA (MI = 1 for a pass of
+// at most 32 coordinates, else 2) and contracts over one chunk of points, 32
+// per step.  The X^T tile (coordinate-major, gathered as in
+// the forward pass, lane = point) is double-buffered in LDS; the rows of G come
+// straight from HBM into the B operand, one step ahead.  Each chunk writes an
+// FP32 partial of the pass's sc rows; alg4_adj_combine adds the chunks in
+// FP64, in chunk order.
+struct AdjArgs {
+  int32_t s, t, tct;
+  int32_t j0, sc, jtiles;          // coordinates [j0, j0 + sc) in tiles of 64
+  int32_t nchunk;
+  int64_t npts, chunk;             // points of the pass; points per chunk (a multiple of 64)
+  int64_t ldg, gstride;            // G: row stride, floats per randomisation
+  int64_t tab_stride, ntiles_tab;  // value tables per randomisation; point tiles of the index words
+};
+
+template <int PREC, int IDX, int MI>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void alg4_adj_kernel(
+    AdjArgs a, DevSpec D, const float *__restrict__ tab, const float *__restrict__ Gm,
+    float *__restrict__ part) {
+  constexpr int TMA = 32 * MI, KPL = 4 * MI;  // coordinates per tile, gathers per lane and step
+  __shared__ float Xs[2][TMA * XPAD];  // two steps of X^T: [coordinate][point]
+  const int tid = threadIdx.x, lane = tid & 63, pl = lane & 31, hh = lane >> 5;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wc = w * 64;
+  int it = blockIdx.x;
+  const int jt = it % a.jtiles;
+  it /= a.jtiles;
+  const int ct = it % a.tct;
+  it /= a.tct;
+  const int ch = it % a.nchunk;
+  const int rl = it / a.nchunk;
+  const int64_t p0 = (int64_t)ch * a.chunk;
+  const int64_t p1 = min(p0 + a.chunk, a.npts);
+  const int64_t nst = p1 > p0 ? (p1 - p0 + TK - 1) / TK : 0;
+  const float *tabr = tab + (int64_t)rl * a.tab_stride;
+  const float *Gr = Gm + (int64_t)rl * a.gstride;
+
+  // this lane's gathers: coordinates 16 MI hh + 4 MI w + q (q < KPL) of the
+  // tile, at point pl of the step (past the pass's coordinates: the last one,
+  // dropped)
+  auto crow = [&](int q) { return 16 * MI * hh + 4 * MI * w + q; };
+  int jq[KPL];
+#pragma unroll
+  for (int q = 0; q < KPL; ++q) jq[q] = a.j0 + min(TMA * jt + crow(q), a.sc - 1);
+  // B element e (as in the forward pass): row (point) kp + brow(e) + bh of G
+  auto brow = [&](int e) { return PREC == QMC_FP32 ? (e & ~1) : (e & ~15) + (e & 7); };
+  auto bblk = [&](int e) { return PREC == QMC_FP32 ? (e & 1) : ((e >> 3) & 1); };
+  const int bh = PREC == QMC_FP32 ? hh : 8 * hh;
+
+  // index words of the step at point kp (a multiple of 32): tile kp / 64, in
+  // which the lane's point is 32 (kp / 32 mod 2) + pl; steps past the chunk
+  // gather valid values (their rows of G read zero)
+  uint32_t yl[KPL], yt[KPL];
+  float xv[KPL];
+  auto load_index = [&](int64_t kp) {
+    const int64_t tn = min(kp >> 6, a.ntiles_tab - 1);
+    const int r = 32 * (int)((kp >> 5) & 1) + pl;
+#pragma unroll
+    for (int q = 0; q < KPL; ++q) {
+      yl[q] = D.ylo[(int64_t)jq[q] * 64 + r];
+      yt[q] = D.ytile[tn * a.s + jq[q]];
+    }
+  };
+  auto load_values = [&](int64_t kp, float (&b)[TK]) {
+    const __amdgpu_buffer_rsrc_t trs = raw_rsrc(tabr, (uint32_t)(a.tab_stride * 4));
+#pragma unroll
+    for (int q = 0; q < KPL; ++q) xv[q] = load_f32(trs, (IDX ? yt[q] + yl[q] : yt[q] ^ yl[q]) << 2);
+    const int64_t left = p1 - kp;  // rows of G of this chunk from row kp on
+    const int64_t want = ((left - 1) * a.ldg + a.t) * 4;
+    const uint32_t bytes = left <= 0 ? 0u : want > 0xffffffffll ? 0xffffffffu : (uint32_t)want;
+    const __amdgpu_buffer_rsrc_t grs = raw_rsrc(left <= 0 ? Gr : Gr + kp * a.ldg, bytes);
+    uint32_t boff[2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+      boff[c] = (uint32_t)(((int64_t)bh * a.ldg + min(ct * TN + wc + 32 * c + pl, a.t - 1)) * 4);
+#pragma unroll
+    for (int e = 0; e < TK; ++e) b[e] = load_f32(grs, (uint32_t)(brow(e) * a.ldg * 4) + boff[bblk(e)]);
+  };
+  auto store_x = [&](float *xs) {
+#pragma unroll
+    for (int q = 0; q < KPL; ++q) xs[crow(q) * XPAD + pl] = xv[q];
+  };
+
+  f32x16 acc[MI][2];
+#pragma unroll
+  for (int i = 0; i < MI; ++i)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) acc[i][c] = f32x16{0};
+
+  // the forward pass's product step: acc[i][c] += (rows 32 i.. of the tile) x
+  // (this wave's columns 32 c..), here rows = coordinates and k = points
+  auto products = [&](const float *xs, const float (&b)[TK]) {
+    if (PREC == QMC_FP32) {
+#pragma unroll
+      for (int kk = 0; kk < TK; kk += 2) {
+        float x[MI];
+#pragma unroll
+        for (int i = 0; i < MI; ++i) x[i] = xs[(32 * i + pl) * XPAD + kk + hh];
+#pragma unroll
+        for (int i = 0; i < MI; ++i)
+#pragma unroll
+          for (int c = 0; c < 2; ++c)
+            acc[i][c] = __builtin_amdgcn_mfma_f32_32x32x2f32(x[i], b[kk + c], acc[i][c], 0, 0, 0);
+      }
+    } else {
+#pragma unroll
+      for (int kc = 0; kc < TK; kc += 16) {
+        const int kq = kc + 8 * hh;
+        bf16x8 xh[MI], xl[MI], bh8[2], bl8[2];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+#pragma unroll
+          for (int i = 0; i < MI; ++i) {
+            const float x = xs[(32 * i + pl) * XPAD + kq + q];
+            const __bf16 hi = (__bf16)x;
+            xh[i][q] = hi;
+            xl[i][q] = (__bf16)(x - (float)hi);
+          }
+#pragma unroll
+          for (int c = 0; c < 2; ++c) {
+            const float v = b[kc + 8 * c + q];
+            const __bf16 hi = (__bf16)v;
+            bh8[c][q] = hi;
+            bl8[c][q] = (__bf16)(v - (float)hi);
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < MI; ++i)
+#pragma unroll
+          for (int c = 0; c < 2; ++c) {
+            acc[i][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xl[i], bh8[c], acc[i][c], 0, 0, 0);
+            acc[i][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[i], bl8[c], acc[i][c], 0, 0, 0);
+            acc[i][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[i], bh8[c], acc[i][c], 0, 0, 0);
+          }
+      }
+    }
+  };
+
+  // steps kp = p0, p0 + 32, ... two per iteration, the operand buffers swapped
+  // by name; a step past the chunk multiplies zero rows of G
+  float bc[TK], bn[TK];
+  load_index(p0);
+  load_values(p0, bc);
+  load_index(p0 + TK);
+  store_x(Xs[0]);
+  __syncthreads();
+  auto step = [&](int64_t kp, const float (&bcur)[TK], float (&bnext)[TK], const float *xcur, float *xnext) {
+    load_values(kp + TK, bnext);
+    load_index(kp + 2 * TK);
+    products(xcur, bcur);
+    store_x(xnext);
+    __syncthreads();
+  };
+  for (int64_t k = 0; k < nst; k += 2) {
+    step(p0 + k * TK, bc, bn, Xs[0], Xs[1]);
+    step(p0 + (k + 1) * TK, bn, bc, Xs[1], Xs[0]);
+  }
+
+  // acc[i][c][v] is element (32 i + 8 (v / 4) + 4 hh + v % 4, wc + 32 c + pl)
+  // of the 32 MI x 256 tile; the partial holds the pass's rows j0 .. j0 + sc - 1
+  float *Pr = part + ((int64_t)rl * a.nchunk + ch) * a.sc * (int64_t)a.t;
+#pragma unroll
+  for (int i = 0; i < MI; ++i)
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int jj = TMA * jt + 32 * i + 8 * (v >> 2) + 4 * hh + (v & 3);
+        const int col = ct * TN + wc + 32 * c + pl;
+        if (jj < a.sc && col < a.t) Pr[(int64_t)jj * a.t + col] = acc[i][c][v];
+      }
+}
+
+// dA[r][j][i] = sum over chunks of the partials, FP64, chunk order: rows
+// j < jlow from the lower pass (plo[r][chunk][j][i], nlo chunks), the others
+// from the upper pass (pup[r][chunk][j - jlow][i], nup chunks).
+__global__ __launch_bounds__(256) void alg4_adj_combine(const float *__restrict__ plo, int nlo,
+                                                        const float *__restrict__ pup, int nup, int s, int jlow,
+                                                        int t, int64_t total, float *__restrict__ dA) {
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+    const int64_t per = (int64_t)s * t;
+    const int64_t rl = e / per, o = e - rl * per;
+    const int64_t j = o / t;
+    const bool lo = j < jlow;
+    const int n = lo ? nlo : nup;
+    const int64_t pper = (int64_t)(lo ? jlow : s - jlow) * t;
+    const float *p = (lo ? plo : pup) + rl * n * pper + (lo ? o : o - (int64_t)jlow * t);
+    double acc = 0.0;
+#pragma unroll 8
+    for (int c = 0; c < n; ++c) acc += (double)p[c * pper];  // eight loads in flight, order kept
+    dA[e] = (float)acc;
+  }
+}
+
+// S[r][rho][i] = sum of G[r][n][i] over n = rho mod nsplit (FP64, increasing n):
+// the sensitivities of the residues of the upper coordinates (n_j | nsplit).
+// V consecutive columns per thread (V = 4 when t is a multiple of 4).
+template <int V>
+__global__ __launch_bounds__(256) void alg4_fold_kernel(const float *__restrict__ Gm, int64_t N, int64_t nsplit,
+                                                        int t, int64_t total, float *__restrict__ S) {
+  typedef float fv __attribute__((ext_vector_type(V)));
+  const int tv = t / V;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+    const int64_t per = nsplit * tv;
+    const int64_t rl = e / per, o = e - rl * per;
+    const int64_t rho = o / tv, cv = o - rho * tv;
+    const fv *g = reinterpret_cast<const fv *>(Gm + rl * N * t) + cv;
+    double acc[V];
+#pragma unroll
+    for (int k = 0; k < V; ++k) acc[k] = 0.0;
+#pragma unroll 4
+    for (int64_t n = rho; n < N; n += nsplit) {
+      const fv x = g[n * tv];
+#pragma unroll
+      for (int k = 0; k < V; ++k) acc[k] += (double)x[k];
+    }
+    fv out;
+#pragma unroll
+    for (int k = 0; k < V; ++k) out[k] = (float)acc[k];
+    reinterpret_cast<fv *>(S + (rl * nsplit + rho) * t)[cv] = out;
+  }
+}
+
+template <int PREC>
+static const void *adj_fn(bool add, int mi) {
+  if (add) return mi == 1 ? reinterpret_cast<const void *>(&alg4_adj_kernel<PREC, 1, 1>)
+                          : reinterpret_cast<const void *>(&alg4_adj_kernel<PREC, 1, 2>);
+  return mi == 1 ? reinterpret_cast<const void *>(&alg4_adj_kernel<PREC, 0, 1>)
+                 : reinterpret_cast<const void *>(&alg4_adj_kernel<PREC, 0, 2>);
+}
+
 template <int PREC, int MODE, int IDX, bool STREAM>
 static const void *fn_g(int gf) {
   if (gf == QMC_G_COS) return reinterpret_cast<const void *>(&alg4_kernel<PREC, MODE, QMC_G_COS, IDX, STREAM>);
@@ -396,6 +673,7 @@ template <int PREC, int IDX, bool STREAM>
 static const void *fn_m(int mode, int gf) {
   if (mode == kModeStoreY) return fn_g<PREC, kModeStoreY, IDX, STREAM>(QMC_G_ID);
   if (mode == kModeSum) return fn_g<PREC, kModeSum, IDX, STREAM>(gf);
+  if (mode == kModeGrad) return fn_g<PREC, kModeGrad, IDX, STREAM>(gf);
   return fn_g<PREC, kModePoint, IDX, STREAM>(gf);
 }
 
@@ -474,7 +752,8 @@ hipError_t launch_alg4(const Geometry &G, const DevSpec &D, int mode, const qmc_
                        int prec, const float *tab, int nr, const float *A, int t, int64_t lda,
                        const Alg4Pass &ps, const Alg4Out &o, hipStream_t st) {
   LaunchTimer tm(ps.timer, st);
-  if (mode != kModeStoreY && mode != kModeSum && mode != kModePoint) return hipErrorInvalidValue;
+  if (mode != kModeStoreY && mode != kModeSum && mode != kModePoint && mode != kModeGrad)
+    return hipErrorInvalidValue;
   // byte offsets of a step's rows of A and of the value tables are 32-bit
   if (lda > kAlg4MaxLda || G.gather_total * 4 > 0xffffffffll) return hipErrorInvalidValue;
   if (ps.sc < 1 || ps.j0 < 0 || ps.j0 + ps.sc > G.s || ps.npts < 1 || ps.npts > G.N ||
@@ -498,6 +777,9 @@ hipError_t launch_alg4(const Geometry &G, const DevSpec &D, int mode, const qmc_
   a.root_stride = ps.root_stride;
   a.nsplit = ps.nsplit;
   a.sigma = g_scale(f, mode);
+  a.gc = (float)f.c;
+  a.gscale = o.gscale;
+  a.hd = o.hd;
   const int64_t nitems = a.ntiles * a.tct * nr;
   if (nitems > 0x7fffffffll) return hipErrorInvalidValue;
   a.nitems = (int32_t)nitems;
@@ -520,6 +802,73 @@ hipError_t launch_alg4(const Geometry &G, const DevSpec &D, int mode, const qmc_
   void *args[] = {&a, &Dv, &tab, &Ap, &Y, &partial, &ppart};
   const hipError_t e = hipLaunchKernel(fn, dim3((unsigned)wgs), dim3(256), args, 0, st);
   return e != hipSuccess ? e : hipGetLastError();
+}
+
+int alg4_adj_chunks(int sc, int64_t npts, int t, int nr) {
+  // about 1024 workgroups over the pass's tiles, chunks of at least 256 points
+  // (8 steps), and at most 2^26 floats of partials
+  if (sc < 1) return 0;
+  const int64_t items = ceil_div(sc, sc <= 32 ? 32 : TM) * alg4_col_tiles(t) * (int64_t)nr;
+  int64_t nch = ceil_div(1024, items);
+  nch = std::min<int64_t>(nch, ceil_div(npts, 256));
+  nch = std::min<int64_t>(nch, (int64_t(1) << 26) / std::max<int64_t>((int64_t)nr * sc * t, 1));
+  return (int)std::max<int64_t>(nch, 1);
+}
+
+hipError_t launch_alg4_adj(const Geometry &G, const DevSpec &D, int prec, const float *tab, int nr,
+                           const float *Gm, int64_t gstride, int j0, int sc, int64_t npts, int nchunk, int t,
+                           float *part, hipStream_t st) {
+  LaunchTimer tm("adjoint", st);
+  if (nr == 0) return hipSuccess;
+  if (sc < 1 || j0 < 0 || j0 + sc > G.s || npts < 1 || npts > G.N || nchunk < 1 || t > kAlg4MaxLda ||
+      G.gather_total * 4 > 0xffffffffll)
+    return hipErrorInvalidValue;
+  AdjArgs a{};
+  a.s = G.s;
+  a.t = t;
+  a.tct = alg4_col_tiles(t);
+  a.j0 = j0;
+  a.sc = sc;
+  const int mi = sc <= 32 ? 1 : 2;
+  a.jtiles = (int)ceil_div(sc, 32 * mi);
+  a.nchunk = nchunk;
+  a.npts = npts;
+  a.chunk = round_up(ceil_div(npts, nchunk), TM);
+  a.ldg = t;
+  a.gstride = gstride;
+  a.tab_stride = G.gather_total;
+  a.ntiles_tab = alg4_point_tiles(G);
+  const int64_t items = (int64_t)a.jtiles * a.tct * nchunk * nr;
+  if (items > 0x7fffffffll) return hipErrorInvalidValue;
+  const bool add = G.b != 2;
+  const void *fn = prec == QMC_FP32 ? adj_fn<QMC_FP32>(add, mi) : adj_fn<QMC_SPLIT_BF16X3>(add, mi);
+  void *args[] = {&a, const_cast<DevSpec *>(&D), &tab, &Gm, &part};
+  const hipError_t e = hipLaunchKernel(fn, dim3((unsigned)items), dim3(256), args, 0, st);
+  return e != hipSuccess ? e : hipGetLastError();
+}
+
+hipError_t launch_alg4_fold(const Geometry &G, const float *Gm, int nr, int t, float *S, hipStream_t st) {
+  LaunchTimer tm("fold", st);
+  const int V = t % 4 == 0 ? 4 : 1;
+  const int64_t total = (int64_t)nr * G.nsub * (t / V);
+  if (total == 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>(ceil_div(total, 256), 16384);
+  if (V == 4)
+    hipLaunchKernelGGL(alg4_fold_kernel<4>, dim3((unsigned)blocks), dim3(256), 0, st, Gm, G.N, G.nsub, t, total, S);
+  else
+    hipLaunchKernelGGL(alg4_fold_kernel<1>, dim3((unsigned)blocks), dim3(256), 0, st, Gm, G.N, G.nsub, t, total, S);
+  return hipGetLastError();
+}
+
+hipError_t launch_alg4_adj_combine(const Geometry &G, const float *plo, int nlo, const float *pup, int nup, int nr,
+                                   int t, float *dA, hipStream_t st) {
+  LaunchTimer tm("combine", st);
+  const int64_t total = (int64_t)G.s * t * nr;
+  if (total == 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>(ceil_div(total, 256), 8192);
+  hipLaunchKernelGGL(alg4_adj_combine, dim3((unsigned)blocks), dim3(256), 0, st, plo, nlo, pup, nup, G.s, G.jlow, t,
+                     total, dA);
+  return hipGetLastError();
 }
 
 }  // namespace qmc

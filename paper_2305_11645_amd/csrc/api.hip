@@ -175,6 +175,7 @@ enum Op { kOpMatvec = 0, kOpEstimate = 1, kOpGrad = 2 };
 
 struct Work {
   float *tables, *U, *ppart, *S, *dlow, *dup, *hd, *root;
+  float *Gm;  // gather path, gradient: the sensitivities G, [nr][N][t]
   double *partial, *ppartial;
 };
 
@@ -196,6 +197,14 @@ size_t carve(const qmc::Geometry &G, int op, int t, const qmc_integrand *f, int 
     if (f->h != QMC_H_ID) {
       wk.ppart = c.take<float>((size_t)nr * atct * G.N);
       wk.ppartial = c.take<double>((size_t)nr * point_h_blocks(G));
+    }
+    if (op == kOpGrad) {  // G, the folded G of the upper coordinates, h', the chunk partials
+      wk.Gm = c.take<float>((size_t)nr * G.N * t);
+      if (G.jlow < G.s) wk.S = c.take<float>((size_t)nr * G.nsub * t);
+      if (f->h != QMC_H_ID) wk.hd = c.take<float>((size_t)nr * G.N);
+      const int nlo = alg4_adj_chunks(G.jlow, G.N, t, nr), nup = alg4_adj_chunks(G.s - G.jlow, G.nsub, t, nr);
+      wk.dlow = c.take<float>((size_t)nr * nlo * G.jlow * t);
+      if (nup > 0) wk.dup = c.take<float>((size_t)nr * nup * (G.s - G.jlow) * t);
     }
     return c.used;
   }
@@ -612,14 +621,14 @@ qmc_status qmc_workspace_size(qmc_points p, int32_t op, int32_t t, const qmc_int
 }
 
 // Gather path: for a base b > 2 with a split, the upper coordinates over the
-// n_split residues into the root table (timed as "levels"), then the lower
-// coordinates over all N points adding the root rows; otherwise one pass.
-static hipError_t gather_passes(const qmc::Geometry &G, const qmc::DevSpec &D, int mode,
-                                const qmc_integrand &f, int prec, const float *tables, int nr,
-                                const float *A, int t, int64_t lda, float *root, const qmc::Alg4Out &o,
-                                hipStream_t st) {
+// n_split residues into the root table (timed as "levels"); `lower` becomes
+// the pass of the lower coordinates over all N points adding the root rows
+// (otherwise the one pass over everything).
+static hipError_t gather_root(const qmc::Geometry &G, const qmc::DevSpec &D, int prec, const float *tables,
+                              int nr, const float *A, int t, int64_t lda, float *root, qmc::Alg4Pass &lower,
+                              hipStream_t st) {
   using namespace qmc;
-  Alg4Pass lower = alg4_whole(G);
+  lower = alg4_whole(G);
   if (G.jlow < G.s) {
     Alg4Pass up{};
     up.j0 = G.jlow;
@@ -639,7 +648,67 @@ static hipError_t gather_passes(const qmc::Geometry &G, const qmc::DevSpec &D, i
     lower.root_stride = G.nsub * t;
     lower.nsplit = G.nsub;
   }
+  return hipSuccess;
+}
+
+static hipError_t gather_passes(const qmc::Geometry &G, const qmc::DevSpec &D, int mode,
+                                const qmc_integrand &f, int prec, const float *tables, int nr,
+                                const float *A, int t, int64_t lda, float *root, const qmc::Alg4Out &o,
+                                hipStream_t st) {
+  using namespace qmc;
+  Alg4Pass lower;
+  const hipError_t e = gather_root(G, D, prec, tables, nr, A, t, lda, root, lower, st);
+  if (e != hipSuccess) return e;
   return launch_alg4(G, D, mode, f, prec, tables, nr, A, t, lda, lower, o, st);
+}
+
+// Gradient on the gather path: the sensitivities G_n = h'(u_n) g'(y_n) / (N t)
+// of every point (a pass over the points in the gradient mode, after the point
+// means when h is not the identity), then dA = X^T G: the lower coordinates
+// over all N points, the upper ones (base b > 2 with a split) over the fold of
+// G into the n_split residues, and the chunk partials added in FP64.
+static hipError_t gather_grad(const qmc::Geometry &G, const qmc::DevSpec &D, const qmc_integrand &f, int prec,
+                              const Work &wk, int nr, const float *A, int t, int64_t lda, double *Q, float *dA,
+                              hipStream_t st) {
+  using namespace qmc;
+  const bool sep = f.h == QMC_H_ID;
+  const double inv_nt = 1.0 / ((double)G.N * (double)t);
+  Alg4Pass lower;
+  hipError_t e = gather_root(G, D, prec, wk.tables, nr, A, t, lda, wk.root, lower, st);
+  if (e != hipSuccess) return e;
+  Alg4Out o{};
+  o.Y = wk.Gm;
+  o.ldy = t;
+  o.ystride = G.N * t;
+  o.gscale = inv_nt;
+  if (sep) {
+    o.partial = wk.partial;
+    if ((e = launch_alg4(G, D, kModeGrad, f, prec, wk.tables, nr, A, t, lda, lower, o, st)) != hipSuccess) return e;
+    if ((e = launch_reduce(wk.partial, nr, alg4_point_tiles(G) * alg4_col_tiles(t), inv_nt, Q, st)) != hipSuccess)
+      return e;
+  } else {
+    Alg4Out op{};
+    op.ppart = wk.ppart;
+    if ((e = launch_alg4(G, D, kModePoint, f, prec, wk.tables, nr, A, t, lda, lower, op, st)) != hipSuccess) return e;
+    const int64_t blocks = point_h_blocks(G);
+    if ((e = launch_point_h(G, f, wk.ppart, nr, alg4_col_tiles(t), t, wk.ppartial, blocks, wk.hd, 1.0, st)) !=
+        hipSuccess)
+      return e;
+    if ((e = launch_reduce(wk.ppartial, nr, blocks, 1.0 / (double)G.N, Q, st)) != hipSuccess) return e;
+    o.hd = wk.hd;
+    if ((e = launch_alg4(G, D, kModeGrad, f, prec, wk.tables, nr, A, t, lda, lower, o, st)) != hipSuccess) return e;
+  }
+  const int nlo = alg4_adj_chunks(G.jlow, G.N, t, nr), nup = alg4_adj_chunks(G.s - G.jlow, G.nsub, t, nr);
+  if ((e = launch_alg4_adj(G, D, prec, wk.tables, nr, wk.Gm, G.N * t, 0, G.jlow, G.N, nlo, t, wk.dlow, st)) !=
+      hipSuccess)
+    return e;
+  if (nup > 0) {
+    if ((e = launch_alg4_fold(G, wk.Gm, nr, t, wk.S, st)) != hipSuccess) return e;
+    if ((e = launch_alg4_adj(G, D, prec, wk.tables, nr, wk.S, G.nsub * t, G.jlow, G.s - G.jlow, G.nsub, nup, t,
+                             wk.dup, st)) != hipSuccess)
+      return e;
+  }
+  return launch_alg4_adj_combine(G, wk.dlow, nlo, wk.dup, nup, nr, t, dA, st);
 }
 
 qmc_status qmc_reduced_matvec(qmc_points p, int32_t r, const float *A, int32_t t, int64_t lda,
@@ -695,10 +764,6 @@ static qmc_status estimate_impl(qmc_points p, const float *A, int32_t t, int64_t
   const Geometry &G = p->G;
   const int nr = G.R;
   const int op = grad ? kOpGrad : kOpEstimate;
-  if (grad && G.gather)
-    return fail(QMC_EUNSUPPORTED, G.nonperiodic
-                    ? "the gradient of a net that is not periodic after reduction (Algorithm 4) is not provided"
-                    : "the gradient in a base b > 2 is not provided");
   Work wk;
   const size_t need = carve(G, op, t, f, nr, nullptr, wk);
   CallWorkspace own;
@@ -714,6 +779,10 @@ static qmc_status estimate_impl(qmc_points p, const float *A, int32_t t, int64_t
 
   if (G.gather) {  // value tables, then the fused tile products
     QMC_HIP(launch_output_tables(G, p->D, 0, nr, wk.tables, st), "tables launch");
+    if (grad) {
+      QMC_HIP(gather_grad(G, p->D, *f, prec, wk, nr, A, t, lda, Q, dA, st), "gradient launch");
+      return QMC_OK;
+    }
     Alg4Out o{};
     if (sep) {
       o.partial = wk.partial;

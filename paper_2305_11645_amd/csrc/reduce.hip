@@ -142,6 +142,8 @@ __global__ __launch_bounds__(256) void combine_kernel(CombineArgs a, const float
     if (j < G.jlow) {
       const int ct = col / kTileT, lane = col % kTileT;
       const int64_t blk = (int64_t)G.jlow * kTileT;
+      // unrolled so that eight loads are in flight (the sum keeps its order)
+#pragma unroll 8
       for (int bx = 0; bx < a.gx; ++bx)
         acc += (double)low[(((int64_t)r * a.gx + bx) * a.tct + ct) * blk + (int64_t)j * kTileT + lane];
     } else {
@@ -149,6 +151,7 @@ __global__ __launch_bounds__(256) void combine_kernel(CombineArgs a, const float
         const Level &L = G.lev[G.up[u]];
         if (j < L.j0 || j >= L.j0 + L.tau) continue;
         const float *p = up + r * a.up_rs + a.poff[u] + (int64_t)(j - L.j0) * a.ldu + col;
+#pragma unroll 8
         for (int c = 0; c < a.kchunks[u]; ++c) acc += (double)p[(int64_t)c * L.tau * a.ldu];
       }
     }
