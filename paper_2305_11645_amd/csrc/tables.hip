@@ -236,7 +236,14 @@ struct TabSeg {
   int64_t dst;          // first table entry of the segment
 };
 
+constexpr int kTabSegPad = 32;  // >= kMaxLevels: the segment starts are scanned in whole batches
+static_assert(kTabSegPad >= kMaxLevels, "segment start table too short");
+
 struct TabArgs {
+  // first block of each segment, contiguous and padded with INT_MAX, so that a
+  // block finds its segment from one batch of scalar loads (a scan through
+  // seg[] would chain one dependent load per segment)
+  int32_t blk0[kTabSegPad];
   int32_t nseg, nblk;
   int32_t rec;          // floats per subtree record
   int32_t sub_sh;       // log2 n_{L'}
@@ -255,9 +262,9 @@ __global__ __launch_bounds__(256) void tables_kernel(TabArgs ta, DevSpec D, int 
     for (int i = threadIdx.x; i < ncounters; i += blockDim.x) counters[i] = 0u;
   const int rl = blockIdx.y;
   int q = 0;
-#pragma unroll 1
-  for (int i = 1; i < ta.nseg; ++i)
-    if ((int)blockIdx.x >= ta.seg[i].blk0) q = i;
+#pragma unroll
+  for (int i = 1; i < kTabSegPad; ++i)
+    if ((int)blockIdx.x >= ta.blk0[i]) q = i;
   const TabSeg sg = ta.seg[q];
   const uint32_t b0 = blockIdx.x - sg.blk0;
   float *o_r = out + (int64_t)rl * ta.table_total + sg.dst;
@@ -365,6 +372,7 @@ hipError_t launch_tables(const Geometry &G, const DevSpec &D, int r0, int nr, fl
     sg.nblk = (int)std::min<int64_t>(ceil_div(sg.count, 256 * kValsPerThread), 512);
     total += sg.nblk;
   }
+  for (int q = 0; q < kTabSegPad; ++q) ta.blk0[q] = q < ta.nseg ? ta.seg[q].blk0 : 0x7fffffff;
   ta.nblk = total;
   if (total == 0) total = 1;  // still zero the counters
   dim3 grid(total, nr);
