@@ -259,7 +259,8 @@ def bench_grad(args, wl) -> int:
         peak = MFMA_PEAK_TFLOPS[prec]
         achieved = mf / (kern["adjoint"]["ms_per_step"] * 1e-3) / 1e12
         roofline = {"bound": "mfma", "kernel": "alg4_adj_kernel", "achieved": round(achieved, 3), "peak": peak,
-                    "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                    "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+                    "traffic": leaf_traffic(args.config, "grad", kernel="alg4_adj_kernel"),
                     "algorithmic_flops": mf}
     flops = 4.0 * wl.N * wl.s * wl.t * wl.R
     out = {"metric": "estimate_grad_dense_equivalent_GFLOPs", "value": round(flops / (ms * 1e-3) / 1e9, 3),
@@ -268,6 +269,7 @@ def bench_grad(args, wl) -> int:
            "config": {"workload": f"C{args.config}", "N": wl.N, "s": wl.s, "t": wl.t, "R": wl.R, "b": wl.b,
                       "split_level": pts.split_level},
            "roofline": roofline, "kernels": kern}
+    calibrate_copy(args.calibrate_copy_mib)
     print(json.dumps(out), flush=True)
     return 0
 

@@ -293,6 +293,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC == QMC
       // (separable f) also the tile's sum of g, as in the summing mode
       float *Gr = Y + (int64_t)rl * a.ystride;
       const float *hk = a.hd ? a.hd + (int64_t)rl * a.N : nullptr;
+      const float gs = (float)a.gscale;
       float sl = 0.f;
 #pragma unroll
       for (int i = 0; i < 2; ++i)
@@ -305,7 +306,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC == QMC
             const int col = colw + 32 * c;
             const float ys = a.sigma * acc[i][c][v];
             if (row < a.N && col < a.t) {
-              Gr[row * a.ldy + col] = (float)(a.gscale * (double)(fac * g_der<GF>(ys, a.gc)));
+              Gr[row * a.ldy + col] = gs * (fac * g_der<GF>(ys, a.gc));
               sl += g_val<GF>(ys);
             }
           }
@@ -440,7 +441,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC == QMC
 struct AdjArgs {
   int32_t s, t, tct;
   int32_t j0, sc, jtiles;          // coordinates [j0, j0 + sc) in tiles of 64
-  int32_t nchunk;
+  int32_t nchunk, ngroups;         // ngroups = column tiles x chunks x randomisations
   int64_t npts, chunk;             // points of the pass; points per chunk (a multiple of 64)
   int64_t ldg, gstride;            // G: row stride, floats per randomisation
   int64_t tab_stride, ntiles_tab;  // value tables per randomisation; point tiles of the index words
@@ -455,9 +456,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void a
   const int tid = threadIdx.x, lane = tid & 63, pl = lane & 31, hh = lane >> 5;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wc = w * 64;
-  int it = blockIdx.x;
-  const int jt = it % a.jtiles;
-  it /= a.jtiles;
+  // The jtiles workgroups of one (column tile, chunk, randomisation) group read
+  // the same rows of G: they run on one XCD (workgroup b runs on XCD b mod 8),
+  // so its L2 fetches those rows once.  Groups past the last are padding.
+  const int xcd = blockIdx.x & 7, k8 = blockIdx.x >> 3;
+  int it = (k8 / a.jtiles) * 8 + xcd;
+  const int jt = k8 % a.jtiles;
+  if (it >= a.ngroups) return;
   const int ct = it % a.tct;
   it /= a.tct;
   const int ch = it % a.nchunk;
@@ -838,8 +843,10 @@ hipError_t launch_alg4_adj(const Geometry &G, const DevSpec &D, int prec, const 
   a.gstride = gstride;
   a.tab_stride = G.gather_total;
   a.ntiles_tab = alg4_point_tiles(G);
-  const int64_t items = (int64_t)a.jtiles * a.tct * nchunk * nr;
+  const int64_t groups = (int64_t)a.tct * nchunk * nr;
+  const int64_t items = round_up(groups, 8) * a.jtiles;  // whole groups of 8 (one per XCD)
   if (items > 0x7fffffffll) return hipErrorInvalidValue;
+  a.ngroups = (int32_t)groups;
   const bool add = G.b != 2;
   const void *fn = prec == QMC_FP32 ? adj_fn<QMC_FP32>(add, mi) : adj_fn<QMC_SPLIT_BF16X3>(add, mi);
   void *args[] = {&a, const_cast<DevSpec *>(&D), &tab, &Gm, &part};
