@@ -318,8 +318,13 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// The summing mode with one column per lane fits eight waves per SIMD in its
+// scalar registers except for cos (its reduction bounds need more; forced to
+// eight waves it spills scalars into vector lanes and runs slower), so it asks
+// for eight: C4 (exp) then runs its 16 waves per SIMD in two full rounds.
 template <int LP, int MODE, int GF, bool FUSE0, int CPL>
-__global__ __launch_bounds__(256) void leaf_kernel(LeafArgs a, const float *__restrict__ tables,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
+    MODE == kModeSum && CPL == 1 && GF != QMC_G_COS ? 8 : 1))) void leaf_kernel(LeafArgs a, const float *__restrict__ tables,
                                                    const float *__restrict__ U,
                                                    const float *__restrict__ A,
                                                    double *__restrict__ partial,
