@@ -181,14 +181,17 @@ __device__ __forceinline__ void descend_lean(float (&y)[CPL][1 << LP], const flo
 
 // Level 0 with a single coordinate, fused with g: leaf c and c + H0 come from
 // the level-1 node c.  The 2 H0 point values are read in halves of at most
-// kBatchFloats.  s[q] receives the FP32 sum of g over the subtree's leaves in
+// kBatchFloats (a quarter for cos).  s[q] receives the FP32 sum of g over the subtree's leaves in
 // column q of the lane.
 template <int LP, int GF, bool NEAR, int CPL>
 __device__ __forceinline__ void leaf_block(const float (&y)[CPL][1 << LP],
                                            const float *__restrict__ x0, const float (&a0)[CPL],
                                            float (&s)[CPL]) {
   constexpr int H0 = (1 << LP) / 2;
-  constexpr int HB = H0 < kBatchFloats / 2 ? H0 : kBatchFloats / 2;
+  // cos needs more scalar registers than the other integrands: half batches
+  // let it fit eight waves per SIMD
+  constexpr int HBF = GF == QMC_G_COS ? kBatchFloats / 4 : kBatchFloats / 2;
+  constexpr int HB = H0 < HBF ? H0 : HBF;
   constexpr int NA = 4;  // independent partial sums per column (breaks the add chain)
   float sp[CPL][NA];
 #pragma unroll
@@ -319,12 +322,11 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // The summing mode with one column per lane fits eight waves per SIMD in its
-// scalar registers except for cos (its reduction bounds need more; forced to
-// eight waves it spills scalars into vector lanes and runs slower), so it asks
-// for eight: C4 (exp) then runs its 16 waves per SIMD in two full rounds.
+// scalar registers (cos with its leaf values read 2 x 8 at a time), so it asks
+// for eight: C2 and C4 then run their 16 waves per SIMD in two full rounds.
 template <int LP, int MODE, int GF, bool FUSE0, int CPL>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
-    MODE == kModeSum && CPL == 1 && GF != QMC_G_COS ? 8 : 1))) void leaf_kernel(LeafArgs a, const float *__restrict__ tables,
+    MODE == kModeSum && CPL == 1 ? 8 : 1))) void leaf_kernel(LeafArgs a, const float *__restrict__ tables,
                                                    const float *__restrict__ U,
                                                    const float *__restrict__ A,
                                                    double *__restrict__ partial,
