@@ -118,9 +118,15 @@ __device__ __forceinline__ uint32_t value_int(const PointConsts &G, const uint32
       if ((rho >> i) & 1u) acc ^= g << i;
     return acc & mask;
   }
+  // digit q of rho selects column q (rho < 2^m: the residue, or the whole
+  // point index of a net that is not periodic).  Every column up to the
+  // highest digit is loaded and masked by its digit, so the loads do not wait
+  // on one another
   const uint32_t *col = gen + (size_t)j * G.m;
+  const int nq = rho ? 32 - __builtin_clz(rho) : 0;
   uint32_t y = 0;
-  for (uint32_t b = rho; b; b &= b - 1u) y ^= col[__builtin_ctz(b)];
+#pragma unroll 4
+  for (int q = 0; q < nq; ++q) y ^= col[q] & (0u - ((rho >> q) & 1u));
   y &= mask;  // rows p > nb of the reduced matrix are zero
   return __builtin_bitreverse32(y) >> (32 - nb);
 }

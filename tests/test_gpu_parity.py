@@ -642,6 +642,23 @@ def test_base_b_gradient(b, m, g, h, c):
     _check_grad(wl, pts)
 
 
+@pytest.mark.parametrize("which", ["net", "base3"])
+def test_gather_path_autograd(which):
+    """QMCEstimate.backward on the gathered-tile paths (a net that is not
+    periodic, a base-3 lattice with the split) returns sum_r gQ_r dQ_r/dA."""
+    torch = torch_cuda()
+    wl = upper_small(m=10, s=50, t=100) if which == "net" else lat_b(3, 6, s=70, t=100)
+    pts = q.Points.from_workload(wl)
+    A = to_dev(wl.A, torch).requires_grad_(True)
+    f = q.Integrand_.of(wl)
+    Q = q.QMCEstimate.apply(A, pts, f, I.FP32)
+    wts = torch.tensor([0.75, -1.25], dtype=torch.float64, device="cuda")
+    (Q * wts).sum().backward()
+    _, dA = q.estimate_grad(pts, A.detach(), f)
+    ref = (wts.view(-1, 1, 1) * dA.double()).sum(0).float()
+    assert torch.allclose(A.grad, ref, rtol=1e-6, atol=1e-12)
+
+
 @pytest.mark.parametrize("kind", [I.POLY_LATTICE, I.DIGITAL_NET, I.IID])
 def test_base_b_gradient_kinds(kind):
     """Polynomial lattices and nets over F_b (digital shift) and reduced Monte
