@@ -245,16 +245,39 @@ __device__ __forceinline__ void descend(float (&y)[1 << LP], const float *__rest
   }
   const float *x = rec + lv.off;
   float a = Alds[lv.j0 * lda_s + lane];
+  // the first coordinate forms the new nodes from their parents, 2 x CH point
+  // values at a time (a whole level-0 block would hold 64 scalar registers)
+  constexpr int CH = H < 16 ? H : 16;
 #pragma unroll
-  for (int c = 0; c < H; ++c) y[c + H] = fmaf(x[c + H], a, y[c]);
+  for (int h0 = 0; h0 < H; h0 += CH) {
+    float xa[CH], xb[CH];
 #pragma unroll
-  for (int c = 0; c < H; ++c) y[c] = fmaf(x[c], a, y[c]);
+    for (int i = 0; i < CH; ++i) {
+      xa[i] = x[h0 + i];
+      xb[i] = x[H + h0 + i];
+    }
+    keep_scalar(xa);
+    keep_scalar(xb);
+#pragma unroll
+    for (int i = 0; i < CH; ++i) {
+      y[h0 + i + H] = fmaf(xb[i], a, y[h0 + i]);
+      y[h0 + i] = fmaf(xa[i], a, y[h0 + i]);
+    }
+  }
 #pragma unroll 1
   for (int jj = 1; jj < tau; ++jj) {
     x += NC;
     a = Alds[(lv.j0 + jj) * lda_s + lane];
+    constexpr int CB = NC < 32 ? NC : 32;
 #pragma unroll
-    for (int c = 0; c < NC; ++c) y[c] = fmaf(x[c], a, y[c]);
+    for (int c0 = 0; c0 < NC; c0 += CB) {
+      float xs[CB];
+#pragma unroll
+      for (int i = 0; i < CB; ++i) xs[i] = x[c0 + i];
+      keep_scalar(xs);
+#pragma unroll
+      for (int i = 0; i < CB; ++i) y[c0 + i] = fmaf(xs[i], a, y[c0 + i]);
+    }
   }
 }
 
