@@ -258,12 +258,17 @@ struct TabArgs {
   TabSeg seg[kMaxLevels];
 };
 
-constexpr int kValsPerThread = 8;
+// Values per thread: the index math and gathers of all of them are issued
+// before their arithmetic.  Two with the inverse normal map, whose FP64
+// evaluation holds many registers per value in flight.
+template <bool INVNORM>
+constexpr int vals_per_thread() { return INVNORM ? 2 : 8; }
 
 template <bool INVNORM>
 __global__ __launch_bounds__(256) void tables_kernel(TabArgs ta, DevSpec D, int r0,
                                                      float *__restrict__ out,
                                                      uint32_t *__restrict__ counters, int ncounters) {
+  constexpr int VPT = vals_per_thread<INVNORM>();
   if (blockIdx.x == 0 && blockIdx.y == 0)
     for (int i = threadIdx.x; i < ncounters; i += blockDim.x) counters[i] = 0u;
   const int rl = blockIdx.y;
@@ -274,12 +279,12 @@ __global__ __launch_bounds__(256) void tables_kernel(TabArgs ta, DevSpec D, int 
   const TabSeg sg = ta.seg[q];
   const uint32_t b0 = blockIdx.x - sg.blk0;
   float *o_r = out + (int64_t)rl * ta.table_total + sg.dst;
-  const uint32_t step = sg.nblk * 256u * kValsPerThread;
-  for (uint32_t base = b0 * 256u * kValsPerThread + threadIdx.x; base < sg.count; base += step) {
+  const uint32_t step = sg.nblk * 256u * VPT;
+  for (uint32_t base = b0 * 256u * VPT + threadIdx.x; base < sg.count; base += step) {
     // all index math and gathers first, then the arithmetic: the loads overlap
-    uint32_t rho[kValsPerThread], jv[kValsPerThread], dst[kValsPerThread];
+    uint32_t rho[VPT], jv[VPT], dst[VPT];
 #pragma unroll
-    for (int v = 0; v < kValsPerThread; ++v) {
+    for (int v = 0; v < VPT; ++v) {
       const uint32_t o = min(base + 256u * v, sg.count - 1);
       uint32_t jj;
       if (sg.lower) {
@@ -296,12 +301,12 @@ __global__ __launch_bounds__(256) void tables_kernel(TabArgs ta, DevSpec D, int 
       }
       jv[v] = sg.j0 + jj;
     }
-    float val[kValsPerThread];
+    float val[VPT];
 #pragma unroll
-    for (int v = 0; v < kValsPerThread; ++v)
+    for (int v = 0; v < VPT; ++v)
       val[v] = (float)value_f64<INVNORM>(ta.G, D, r0 + rl, (int)jv[v], rho[v], sg.nb);
 #pragma unroll
-    for (int v = 0; v < kValsPerThread; ++v)
+    for (int v = 0; v < VPT; ++v)
       if (base + 256u * v < sg.count) o_r[dst[v]] = val[v];
   }
 }
@@ -361,6 +366,7 @@ hipError_t launch_tables(const Geometry &G, const DevSpec &D, int r0, int nr, fl
   ta.rec = (int)G.rec;
   ta.sub_sh = G.m - G.split;
   ta.table_total = G.table_total;
+  const int vpt = G.map == QMC_MAP_INVNORM ? vals_per_thread<true>() : vals_per_thread<false>();
   int total = 0;
   for (int q = 0; q < ta.nseg; ++q) {
     const bool lower = q < G.split;
@@ -375,7 +381,7 @@ hipError_t launch_tables(const Geometry &G, const DevSpec &D, int r0, int nr, fl
     sg.nb = L.nb;
     sg.dst = lower ? L.off : G.lower_total + L.off;
     sg.blk0 = total;
-    sg.nblk = (int)std::min<int64_t>(ceil_div(sg.count, 256 * kValsPerThread), 512);
+    sg.nblk = (int)std::min<int64_t>(ceil_div(sg.count, 256 * vpt), 512);
     total += sg.nblk;
   }
   for (int q = 0; q < kTabSegPad; ++q) ta.blk0[q] = q < ta.nseg ? ta.seg[q].blk0 : 0x7fffffff;
