@@ -798,3 +798,20 @@ def test_alg4_gradient_equals_dense(oracle_lib, g, h):
     for r in range(wl.R):
         ref = _dense_grad(wl, A, brute.point_matrix(wl, r), r)
         assert np.linalg.norm(dA[r] - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+def test_alg4_gradient_finite_differences(oracle_lib):
+    """For a net that is not periodic, central differences of the oracle
+    estimate along a random direction V agree with <dA, V>."""
+    O = oracle_lib
+    wl = upper_net(m=8, s=16, t=6, R=1, mp=I.MAP_CENTER, g=I.G_EXP, h=I.H_ID)
+    wl.c = 0.4
+    A = wl.A.astype(np.float64)
+    _, dA = O.estimate_grad(wl, A=A)
+    V = np.random.default_rng(5).standard_normal(A.shape)
+    eps = 1e-5
+    qp, _ = O.estimate(wl, A=A + eps * V)
+    qm, _ = O.estimate(wl, A=A - eps * V)
+    fd = (qp[0] - qm[0]) / (2 * eps)
+    an = float(np.sum(dA[0] * V))
+    assert abs(fd - an) <= 1e-8 * max(1.0, abs(an))
