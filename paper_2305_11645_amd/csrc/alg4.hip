@@ -435,9 +435,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC == QMC
 // at most 32 coordinates, else 2) and contracts over one chunk of points, 32
 // per step.  The X^T tile (coordinate-major, gathered as in
 // the forward pass, lane = point) is double-buffered in LDS; the rows of G come
-// straight from HBM into the B operand, one step ahead.  Each chunk writes an
-// FP32 partial of the pass's sc rows; alg4_adj_combine adds the chunks in
-// FP64, in chunk order.
+// straight from HBM into the B operand, one step ahead.  The matrix cores
+// accumulate in FP32 over at most kAdjFlushPoints points; then the
+// accumulators are added into the chunk's FP64 partial of the pass's sc rows
+// (owned by this workgroup alone) and restart from zero, so no FP32 sum runs
+// over more than kAdjFlushPoints terms whatever the chunk size.
+// alg4_adj_combine adds the chunks in FP64, in chunk order.
 struct AdjArgs {
   int32_t s, t, tct;
   int32_t j0, sc, jtiles;          // coordinates [j0, j0 + sc) in tiles of 64
@@ -447,10 +450,13 @@ struct AdjArgs {
   int64_t tab_stride, ntiles_tab;  // value tables per randomisation; point tiles of the index words
 };
 
+constexpr int kAdjFlushSteps = kAdjFlushPoints / TK;
+static_assert(kAdjFlushSteps % 2 == 0, "the step loop advances two steps at a time");
+
 template <int PREC, int IDX, int MI>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void alg4_adj_kernel(
     AdjArgs a, DevSpec D, const float *__restrict__ tab, const float *__restrict__ Gm,
-    float *__restrict__ part) {
+    double *__restrict__ part) {
   constexpr int TMA = 32 * MI, KPL = 4 * MI;  // coordinates per tile, gathers per lane and step
   __shared__ float Xs[2][TMA * XPAD];  // two steps of X^T: [coordinate][point]
   const int tid = threadIdx.x, lane = tid & 63, pl = lane & 31, hh = lane >> 5;
@@ -589,31 +595,43 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void a
     store_x(xnext);
     __syncthreads();
   };
-  for (int64_t k = 0; k < nst; k += 2) {
-    step(p0 + k * TK, bc, bn, Xs[0], Xs[1]);
-    step(p0 + (k + 1) * TK, bn, bc, Xs[1], Xs[0]);
-  }
-
   // acc[i][c][v] is element (32 i + 8 (v / 4) + 4 hh + v % 4, wc + 32 c + pl)
   // of the 32 MI x 256 tile; the partial holds the pass's rows j0 .. j0 + sc - 1
-  float *Pr = part + ((int64_t)rl * a.nchunk + ch) * a.sc * (int64_t)a.t;
+  double *Pr = part + ((int64_t)rl * a.nchunk + ch) * a.sc * (int64_t)a.t;
+  auto flush = [&](bool first) {
 #pragma unroll
-  for (int i = 0; i < MI; ++i)
+    for (int i = 0; i < MI; ++i)
 #pragma unroll
-    for (int c = 0; c < 2; ++c)
+      for (int c = 0; c < 2; ++c) {
 #pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const int jj = TMA * jt + 32 * i + 8 * (v >> 2) + 4 * hh + (v & 3);
-        const int col = ct * TN + wc + 32 * c + pl;
-        if (jj < a.sc && col < a.t) Pr[(int64_t)jj * a.t + col] = acc[i][c][v];
+        for (int v = 0; v < 16; ++v) {
+          const int jj = TMA * jt + 32 * i + 8 * (v >> 2) + 4 * hh + (v & 3);
+          const int col = ct * TN + wc + 32 * c + pl;
+          if (jj < a.sc && col < a.t) {
+            double *d = Pr + (int64_t)jj * a.t + col;
+            *d = (first ? 0.0 : *d) + (double)acc[i][c][v];
+          }
+        }
+        acc[i][c] = f32x16{0};
       }
+  };
+  // sub-chunks of kAdjFlushSteps steps (an even count, so only the last
+  // sub-chunk can run one step past the chunk: that step reads zero rows of G)
+  for (int64_t k0 = 0; k0 < nst || k0 == 0; k0 += kAdjFlushSteps) {
+    const int64_t k1 = min(k0 + (int64_t)kAdjFlushSteps, nst);
+    for (int64_t k = k0; k < k1; k += 2) {
+      step(p0 + k * TK, bc, bn, Xs[0], Xs[1]);
+      step(p0 + (k + 1) * TK, bn, bc, Xs[1], Xs[0]);
+    }
+    flush(k0 == 0);
+  }
 }
 
 // dA[r][j][i] = sum over chunks of the partials, FP64, chunk order: rows
 // j < jlow from the lower pass (plo[r][chunk][j][i], nlo chunks), the others
 // from the upper pass (pup[r][chunk][j - jlow][i], nup chunks).
-__global__ __launch_bounds__(256) void alg4_adj_combine(const float *__restrict__ plo, int nlo,
-                                                        const float *__restrict__ pup, int nup, int s, int jlow,
+__global__ __launch_bounds__(256) void alg4_adj_combine(const double *__restrict__ plo, int nlo,
+                                                        const double *__restrict__ pup, int nup, int s, int jlow,
                                                         int t, int64_t total, float *__restrict__ dA) {
   for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
     const int64_t per = (int64_t)s * t;
@@ -622,10 +640,10 @@ __global__ __launch_bounds__(256) void alg4_adj_combine(const float *__restrict_
     const bool lo = j < jlow;
     const int n = lo ? nlo : nup;
     const int64_t pper = (int64_t)(lo ? jlow : s - jlow) * t;
-    const float *p = (lo ? plo : pup) + rl * n * pper + (lo ? o : o - (int64_t)jlow * t);
+    const double *p = (lo ? plo : pup) + rl * n * pper + (lo ? o : o - (int64_t)jlow * t);
     double acc = 0.0;
 #pragma unroll 8
-    for (int c = 0; c < n; ++c) acc += (double)p[c * pper];  // eight loads in flight, order kept
+    for (int c = 0; c < n; ++c) acc += p[c * pper];  // eight loads in flight, order kept
     dA[e] = (float)acc;
   }
 }
@@ -811,7 +829,7 @@ hipError_t launch_alg4(const Geometry &G, const DevSpec &D, int mode, const qmc_
 
 int alg4_adj_chunks(int sc, int64_t npts, int t, int nr) {
   // about 1024 workgroups over the pass's tiles, chunks of at least 256 points
-  // (8 steps), and at most 2^26 floats of partials
+  // (8 steps), and at most 2^26 FP64 partials
   if (sc < 1) return 0;
   const int64_t items = ceil_div(sc, sc <= 32 ? 32 : TM) * alg4_col_tiles(t) * (int64_t)nr;
   int64_t nch = ceil_div(1024, items);
@@ -822,7 +840,7 @@ int alg4_adj_chunks(int sc, int64_t npts, int t, int nr) {
 
 hipError_t launch_alg4_adj(const Geometry &G, const DevSpec &D, int prec, const float *tab, int nr,
                            const float *Gm, int64_t gstride, int j0, int sc, int64_t npts, int nchunk, int t,
-                           float *part, hipStream_t st) {
+                           double *part, hipStream_t st) {
   LaunchTimer tm("adjoint", st);
   if (nr == 0) return hipSuccess;
   if (sc < 1 || j0 < 0 || j0 + sc > G.s || npts < 1 || npts > G.N || nchunk < 1 || t > kAlg4MaxLda ||
@@ -867,7 +885,7 @@ hipError_t launch_alg4_fold(const Geometry &G, const float *Gm, int nr, int t, f
   return hipGetLastError();
 }
 
-hipError_t launch_alg4_adj_combine(const Geometry &G, const float *plo, int nlo, const float *pup, int nup, int nr,
+hipError_t launch_alg4_adj_combine(const Geometry &G, const double *plo, int nlo, const double *pup, int nup, int nr,
                                    int t, float *dA, hipStream_t st) {
   LaunchTimer tm("combine", st);
   const int64_t total = (int64_t)G.s * t * nr;

@@ -177,6 +177,7 @@ struct Work {
   float *tables, *U, *ppart, *S, *dlow, *dup, *hd, *root;
   float *Gm;  // gather path, gradient: the sensitivities G, [nr][N][t]
   double *partial, *ppartial;
+  double *glow, *gup;  // gather path, gradient: FP64 chunk partials of dA
 };
 
 size_t carve(const qmc::Geometry &G, int op, int t, const qmc_integrand *f, int nr, char *base,
@@ -203,8 +204,8 @@ size_t carve(const qmc::Geometry &G, int op, int t, const qmc_integrand *f, int 
       if (G.jlow < G.s) wk.S = c.take<float>((size_t)nr * G.nsub * t);
       if (f->h != QMC_H_ID) wk.hd = c.take<float>((size_t)nr * G.N);
       const int nlo = alg4_adj_chunks(G.jlow, G.N, t, nr), nup = alg4_adj_chunks(G.s - G.jlow, G.nsub, t, nr);
-      wk.dlow = c.take<float>((size_t)nr * nlo * G.jlow * t);
-      if (nup > 0) wk.dup = c.take<float>((size_t)nr * nup * (G.s - G.jlow) * t);
+      wk.glow = c.take<double>((size_t)nr * nlo * G.jlow * t);
+      if (nup > 0) wk.gup = c.take<double>((size_t)nr * nup * (G.s - G.jlow) * t);
     }
     return c.used;
   }
@@ -461,8 +462,16 @@ qmc_status qmc_points_init(qmc_points *out, const qmc_point_spec *sp) {
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(QMC_EDEVICE, "no HIP device");
 
+  int device = 0;
+  QMC_HIP(hipGetDevice(&device), "hipGetDevice");
+  // value tables of the gather path: their byte offsets are 32-bit in the kernels
+  const int64_t gather_total = nonperiodic ? sample_total : b != 2 ? 2 * sample_total : 0;
+  if (gather_total >= kAlg4MaxValues)
+    return fail(QMC_EUNSUPPORTED, "value tables of %lld floats reach %lld", (long long)gather_total,
+                (long long)kAlg4MaxValues);
+
   qmc_points p = new qmc_points_s();
-  QMC_HIP(hipGetDevice(&p->device), "hipGetDevice");
+  p->device = device;
   qmc::Geometry &G = p->G;
   G.m = m;
   G.s = s;
@@ -477,10 +486,7 @@ qmc_status qmc_points_init(qmc_points *out, const qmc_point_spec *sp) {
   G.gather = nonperiodic || b != 2 ? 1 : 0;
   if (nonperiodic) G.jlow = s;  // one pass over every coordinate
   if (b != 2) plan_gather_split(G, sp->w, Nb);
-  G.gather_total = nonperiodic ? sample_total : b != 2 ? 2 * sample_total : 0;
-  if (G.gather_total > kAlg4MaxValues)
-    return fail(QMC_EUNSUPPORTED, "value tables of %lld floats exceed %lld", (long long)G.gather_total,
-                (long long)kAlg4MaxValues);
+  G.gather_total = gather_total;
 
   auto cleanup = [&](qmc_status st) {
     qmc_points_free(p);
@@ -699,16 +705,16 @@ static hipError_t gather_grad(const qmc::Geometry &G, const qmc::DevSpec &D, con
     if ((e = launch_alg4(G, D, kModeGrad, f, prec, wk.tables, nr, A, t, lda, lower, o, st)) != hipSuccess) return e;
   }
   const int nlo = alg4_adj_chunks(G.jlow, G.N, t, nr), nup = alg4_adj_chunks(G.s - G.jlow, G.nsub, t, nr);
-  if ((e = launch_alg4_adj(G, D, prec, wk.tables, nr, wk.Gm, G.N * t, 0, G.jlow, G.N, nlo, t, wk.dlow, st)) !=
+  if ((e = launch_alg4_adj(G, D, prec, wk.tables, nr, wk.Gm, G.N * t, 0, G.jlow, G.N, nlo, t, wk.glow, st)) !=
       hipSuccess)
     return e;
   if (nup > 0) {
     if ((e = launch_alg4_fold(G, wk.Gm, nr, t, wk.S, st)) != hipSuccess) return e;
     if ((e = launch_alg4_adj(G, D, prec, wk.tables, nr, wk.S, G.nsub * t, G.jlow, G.s - G.jlow, G.nsub, nup, t,
-                             wk.dup, st)) != hipSuccess)
+                             wk.gup, st)) != hipSuccess)
       return e;
   }
-  return launch_alg4_adj_combine(G, wk.dlow, nlo, wk.dup, nup, nr, t, dA, st);
+  return launch_alg4_adj_combine(G, wk.glow, nlo, wk.gup, nup, nr, t, dA, st);
 }
 
 qmc_status qmc_reduced_matvec(qmc_points p, int32_t r, const float *A, int32_t t, int64_t lda,

@@ -250,22 +250,25 @@ int64_t alg4_point_tiles(const Geometry &G);
 int64_t alg4_index_words(const Geometry &G);  // (64 + tiles) * s
 int alg4_col_tiles(int t);
 constexpr int64_t kAlg4MaxLda = int64_t(1) << 24;     // leading dimension of A
-constexpr int64_t kAlg4MaxValues = int64_t(1) << 30;  // sum_j n_j
+constexpr int64_t kAlg4MaxValues = int64_t(1) << 30;  // value-table floats: below 2^30 (4-byte offsets < 2^32)
 // Adjoint of the gather path, dA = X^T G (Algorithm 4 transposed).
 // alg4_adj_chunks: point chunks of a pass over sc coordinates and npts points
-// (its partials hold nr x chunks x sc x t floats).  launch_alg4_adj:
+// (its partials hold nr x chunks x sc x t FP64 values).  launch_alg4_adj:
 // coordinates [j0, j0 + sc) over the first npts rows of G ([randomisation][npts
 // rows of t], gstride floats apart) into part[r][chunk][j - j0][i].
 // launch_alg4_fold: S[r][rho] = sum of G[r][n] over n = rho mod nsplit
 // (Geometry::nsub).  launch_alg4_adj_combine: dA[r][j][i] = FP64 sum of the
 // chunks' partials, rows j < jlow from the lower pass's, the others from the
 // upper pass's.
+// The partials are FP64: within a chunk the matrix cores sum in FP32 over at
+// most kAdjFlushPoints points at a time, then add into the chunk's partial.
+constexpr int kAdjFlushPoints = 4096;
 int alg4_adj_chunks(int sc, int64_t npts, int t, int nr);
 hipError_t launch_alg4_adj(const Geometry &G, const DevSpec &D, int prec, const float *tab, int nr,
                            const float *Gm, int64_t gstride, int j0, int sc, int64_t npts, int nchunk, int t,
-                           float *part, hipStream_t st);
+                           double *part, hipStream_t st);
 hipError_t launch_alg4_fold(const Geometry &G, const float *Gm, int nr, int t, float *S, hipStream_t st);
-hipError_t launch_alg4_adj_combine(const Geometry &G, const float *plo, int nlo, const float *pup, int nup, int nr,
+hipError_t launch_alg4_adj_combine(const Geometry &G, const double *plo, int nlo, const double *pup, int nup, int nr,
                                    int t, float *dA, hipStream_t st);
 hipError_t launch_alg4_index(const Geometry &G, const uint32_t *gen, const int32_t *nbj, const uint32_t *aoff,
                              uint32_t *ylo, uint32_t *ytile, hipStream_t st);
