@@ -226,6 +226,21 @@ qmc_status qmc_estimate(qmc_points p, const float *A, int32_t t, int64_t lda, co
                         int32_t prec, double *Q, void *workspace, size_t workspace_bytes, void *stream);
 
 /*
+ * qmc_estimate for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same computation and the same kernels, with the workspace taken from a
+ * static device array of 64 MiB that the library holds on every device it
+ * runs on until the process ends.  Makes no allocation of any kind.
+ * Returns QMC_ENOMEM, before anything is launched, when the call needs more
+ * than 64 MiB of workspace (qmc_workspace_size with op = 1 tells).  Every call
+ * on one device shares that device's array: calls that overlap in time on one
+ * device (other streams, other threads) race and must be serialised by the
+ * caller.  The results equal those of qmc_estimate bit for bit.
+ */
+qmc_status qmc_estimate_static(qmc_points p, const float *A, int32_t t, int64_t lda,
+                               const qmc_integrand *f, int32_t prec, double *Q, void *stream);
+
+/*
  * Q as qmc_estimate, and dA[r] = dQ_r/dA = N^-1 sum_k x_k (x) grad f(x_k^T A)
  * for every r: the transpose of the reduced product (sums of the point-wise
  * sensitivities over the residue classes k mod n_j, then the distinct values),

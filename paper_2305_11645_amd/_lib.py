@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(HERE, "libqmcred.so")
 EXPORTS = [
     "qmc_points_init", "qmc_points_free", "qmc_points_info", "qmc_point_values",
     "qmc_point_matrix", "qmc_workspace_size", "qmc_reduced_matvec", "qmc_estimate",
+    "qmc_estimate_static",
     "qmc_estimate_grad", "qmc_status_string", "qmc_last_error", "qmc_timing_enable",
     "qmc_timing_reset", "qmc_timing_read",
 ]
@@ -55,6 +56,7 @@ def load() -> ct.CDLL:
     L.qmc_workspace_size.argtypes = [vp, i32, i32, ct.POINTER(Integrand), i32, ct.POINTER(sz)]
     L.qmc_reduced_matvec.argtypes = [vp, i32, vp, i32, i64, i32, vp, i64, vp, sz, vp]
     L.qmc_estimate.argtypes = [vp, vp, i32, i64, ct.POINTER(Integrand), i32, vp, vp, sz, vp]
+    L.qmc_estimate_static.argtypes = [vp, vp, i32, i64, ct.POINTER(Integrand), i32, vp, vp]
     L.qmc_estimate_grad.argtypes = [vp, vp, i32, i64, ct.POINTER(Integrand), i32, vp, vp, vp, sz, vp]
     L.qmc_status_string.argtypes = [i32]
     L.qmc_status_string.restype = ct.c_char_p

@@ -236,6 +236,34 @@ struct CallWorkspace {
   }
 };
 
+// Workspace of qmc_estimate_static: one array per device for the life of the
+// process.  Host code never uses the array's name as an address (on the host
+// it is only a stand-in for the symbol): static_scratch() looks up its device
+// address once per device, with that device current, and every use goes
+// through the address found.
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) char scratch[kStaticScratchBytes];
+
+std::mutex g_scratch_mu;
+std::unordered_map<int, void *> g_scratch_ptr;  // device -> device address of scratch
+
+// The device address of `scratch` on `device` (which the caller has made current).
+qmc_status static_scratch(int device, void **out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_ptr.find(device);
+  if (it == g_scratch_ptr.end()) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || ptr == nullptr) {
+      return fail(QMC_EDEVICE, "static scratch address on device %d: %s", device,
+                  e != hipSuccess ? hipGetErrorString(e) : "null address");
+    }
+    it = g_scratch_ptr.emplace(device, ptr).first;
+  }
+  *out = it->second;
+  return QMC_OK;
+}
+
 qmc_status check_points(qmc_points p) {
   if (!p) return fail(QMC_EINVAL, "null point set");
   return QMC_OK;
@@ -850,6 +878,24 @@ static qmc_status estimate_impl(qmc_points p, const float *A, int32_t t, int64_t
 qmc_status qmc_estimate(qmc_points p, const float *A, int32_t t, int64_t lda, const qmc_integrand *f,
                         int32_t prec, double *Q, void *workspace, size_t workspace_bytes, void *stream) {
   return estimate_impl(p, A, t, lda, f, prec, Q, nullptr, workspace, workspace_bytes, stream);
+}
+
+qmc_status qmc_estimate_static(qmc_points p, const float *A, int32_t t, int64_t lda,
+                               const qmc_integrand *f, int32_t prec, double *Q, void *stream) {
+  using namespace qmc;
+  if (qmc_status st = check_points(p)) return st;
+  if (qmc_status st = check_matrix(A, t, lda, prec)) return st;
+  if (qmc_status st = check_integrand(f)) return st;
+  if (!Q) return fail(QMC_EINVAL, "Q is null");
+  DeviceGuard dg(p->device);
+  Work wk;
+  const size_t need = carve(p->G, kOpEstimate, t, f, p->G.R, nullptr, wk);
+  if (need > kStaticScratchBytes)
+    return fail(QMC_ENOMEM, "the estimate needs %zu bytes of workspace; the static scratch holds %zu",
+                need, (size_t)kStaticScratchBytes);
+  void *ws = nullptr;
+  if (qmc_status st = static_scratch(p->device, &ws)) return st;
+  return estimate_impl(p, A, t, lda, f, prec, Q, nullptr, ws, kStaticScratchBytes, stream);
 }
 
 qmc_status qmc_estimate_grad(qmc_points p, const float *A, int32_t t, int64_t lda,
