@@ -25,14 +25,20 @@ sys.path.insert(0, ROOT)
 
 import numpy as np  # noqa: E402
 
-# MI355X FP32 vector peak 157.3 TFLOP/s = 256 CUs x 128 FP32 lanes x 2.4 GHz x
-# 2 flops: 7.86e13 FMA lane-slots/s.  A transcendental (v_cos, v_sin, v_exp)
-# issues at a quarter of that rate, i.e. costs 4 slots (measured on the GPU:
-# cos 16.8e12/s, 85% of the quarter rate).  Achieved = 2 x algorithmic slots /
-# duration, in FP32-FMA-equivalent TFLOP/s, against 157.3.
-VALU_SLOTS_PER_S = 256 * 128 * 2.4e9
+# ALU roofline.  MI355X's FP32 vector peak of 157.3 TFLOP/s counts the packed
+# form v_pk_fma_f32 (two FP32 operations per lane and instruction).  This
+# library is built without packed FP32 instructions (-packed-fp32-ops), so the
+# unit count that bounds it is 256 CUs x 4 SIMDs x 16 lanes = 64 FP32 lanes
+# per CU and clock: 256 x 64 x 2.4 GHz = 3.93e13 FMA lane-slots/s, 78.6 TFLOP/s
+# (the same as the FP64 vector peak).  A transcendental (v_exp_f32, v_sin_f32,
+# v_cos_f32) issues at half the FMA rate (qmc_probe_valu measures both on the
+# box; the line carries the measured rates), so it costs 2 slots.  Achieved =
+# 2 x algorithmic slots / duration, in FMA-equivalent TFLOP/s, against 78.6;
+# the fraction against the packed 157.3 is reported beside it.
+VALU_SLOTS_PER_S = 256 * 64 * 2.4e9
 VALU_PEAK_TFLOPS = 2 * VALU_SLOTS_PER_S / 1e12
-G_SLOTS = {0: 0, 1: 4, 2: 4}  # per evaluation of g: id; cos; exp (one transcendental)
+VALU_PACKED_PEAK_TFLOPS = 157.3
+G_SLOTS = {0: 0, 1: 2, 2: 2}  # per evaluation of g: id; cos; exp (one transcendental)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 MFMA_PEAK_TFLOPS = {0: 157.3, 1: 2500.0}  # dense FP32 and BF16 matrix-core peaks
 
@@ -63,13 +69,62 @@ def leaf_algorithmic_slots(wl, split: int) -> float:
     """VALU lane slots the fused leaf pass must spend per launch (all shifts):
     the lower-level multiply-adds t R sum_{j: min(w_j,m) < L'} n_j (Theorem 2's
     count on those coordinates), one add per subtree root and upper level, and
-    per point and column one g (a transcendental: 4 slots) and one accumulation."""
+    per point and column one g (a transcendental: 2 slots) and one accumulation."""
     m, t, R, N = wl.m, wl.t, wl.R, wl.N
     lev = np.minimum(wl.w, m)
     nlow = sum(2 ** (m - int(I)) for I in lev if I < split)
     nup = len({int(I) for I in lev if I >= split})
     nsub = 2 ** (m - split)
     return float(t * R * nlow + t * R * nsub * nup + N * t * R * (1 + G_SLOTS[wl.g]))
+
+
+def grad_leaf_algorithmic_slots(wl, split: int) -> float:
+    """VALU lane slots of the gradient-mode leaf pass per launch (all shifts):
+    the lower-level multiply-adds forward and transposed, 2 t R sum_low n_j; one
+    add per subtree root and upper level; per point and column g' (one
+    transcendental, 2 slots, none for g = y) and, for separable h, g (shared
+    with g' for exp) and its accumulation, else the factor h'; the folds of the
+    transposed recursion (2^{L'} - 1 adds per subtree and column); and one
+    accumulation per lower coordinate, subtree and column."""
+    m, t, R, N = wl.m, wl.t, wl.R, wl.N
+    lev = np.minimum(wl.w, m)
+    nlow = sum(2 ** (m - int(I)) for I in lev if I < split)
+    jlow = int(sum(1 for I in lev if I < split))
+    nup = len({int(I) for I in lev if I >= split})
+    nsub = 2 ** (m - split)
+    per_point = G_SLOTS[wl.g]
+    if wl.h == 0:
+        per_point += (G_SLOTS[wl.g] if wl.g == 1 else 0) + 1
+    else:
+        per_point += 1
+    return float(2 * t * R * nlow + t * R * nsub * nup + N * t * R * per_point
+                 + t * R * nsub * (2 ** split - 1) + t * R * nsub * jlow)
+
+
+_VALU_RATES = None
+
+
+def measured_valu():
+    """The VALU issue rates measured on this GPU (qmc_probe_valu), in T lane-ops/s."""
+    global _VALU_RATES
+    if _VALU_RATES is None:
+        import paper_2305_11645_amd as q
+        r = q.probe_valu()
+        _VALU_RATES = {k: round(v / 1e12, 2) for k, v in r.items()}
+    return _VALU_RATES
+
+
+def alu_roofline(kernel: str, achieved: float, slots: float, avg_ms: float, traffic):
+    """The roofline object of an ALU-bound kernel: achieved FMA-equivalent
+    TFLOP/s against the unpacked FP32 peak, with the packed-peak fraction and the
+    rates measured on this GPU beside it."""
+    return {"bound": "alu", "kernel": kernel, "achieved": round(achieved, 3),
+            "peak": round(VALU_PEAK_TFLOPS, 1), "unit": "TFLOP/s",
+            "frac": round(achieved / VALU_PEAK_TFLOPS, 4), "traffic": traffic,
+            "avg_ms": round(avg_ms, 5), "algorithmic_lane_ops": slots,
+            "peak_note": "unpacked FP32: 256 CUs x 64 lanes x 2 flops x 2.4 GHz; transcendentals 2 slots",
+            "frac_vs_packed_peak_157.3": round(achieved / VALU_PACKED_PEAK_TFLOPS, 4),
+            "measured_rates_T_per_s": measured_valu()}
 
 
 def calibrate_copy(mib: int) -> None:
@@ -245,7 +300,7 @@ def bench_grad(args, wl) -> int:
     torch.cuda.synchronize()
     q.timing.enable(False)
     kern = {}
-    for name in ("tables", "levels", "leaf", "reduce", "levels_adj", "adjoint", "fold", "combine"):
+    for name in ("tables", "levels", "leaf", "leaf_grad", "reduce", "levels_adj", "adjoint", "fold", "combine"):
         tot, n = q.timing.read(name)
         if n:
             kern[name] = {"ms_per_step": tot / args.steps, "launches": n}
@@ -264,6 +319,12 @@ def bench_grad(args, wl) -> int:
                     "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
                     "traffic": leaf_traffic(args.config, "grad", kernel="alg4_adj_kernel"),
                     "algorithmic_flops": mf}
+    elif "leaf_grad" in kern:
+        # the tree path: the gradient-mode leaf pass is the dominant kernel
+        lms = kern["leaf_grad"]["ms_per_step"] * args.steps / kern["leaf_grad"]["launches"]
+        slots = grad_leaf_algorithmic_slots(wl, pts.split_level)
+        roofline = alu_roofline("grad_kernel (leaf, gradient mode)", 2 * slots / (lms * 1e-3) / 1e12, slots, lms,
+                                leaf_traffic(args.config, "grad", kernel="grad_kernel"))
     flops = 4.0 * wl.N * wl.s * wl.t * wl.R
     out = {"metric": "estimate_grad_dense_equivalent_GFLOPs", "value": round(flops / (ms * 1e-3) / 1e9, 3),
            "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 5),
@@ -425,10 +486,7 @@ def bench_estimate(args, wl) -> int:
     else:
         slots = leaf_algorithmic_slots(wl, pts.split_level)
         achieved = 2 * slots / (leaf_ms * 1e-3) / 1e12
-        roofline = {"bound": "alu", "kernel": "leaf_kernel", "achieved": round(achieved, 3),
-                    "peak": round(VALU_PEAK_TFLOPS, 1), "unit": "TFLOP/s",
-                    "frac": round(achieved / VALU_PEAK_TFLOPS, 4), "traffic": leaf_traffic(args.config),
-                    "avg_ms": round(leaf_ms, 5), "algorithmic_lane_ops": slots}
+        roofline = alu_roofline("leaf_kernel", achieved, slots, leaf_ms, leaf_traffic(args.config))
 
     dense = None
     if not args.no_dense:

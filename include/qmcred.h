@@ -273,6 +273,15 @@ const char *qmc_last_error(void);
  * records to the stream.
  */
 qmc_status qmc_timing_enable(int32_t on);
+/*
+ * Measured issue rates of the vector ALU on the current device, for the
+ * roofline of the ALU-bound kernels: lane operations per second of FP32
+ * v_fma_f32 (the unpacked form, the only FP32 form this library emits), of
+ * v_exp_f32 (each followed by one v_mul_f32) and of v_sin_f32.  Runs short
+ * timed kernels on `stream` (allocates and frees a small buffer; synchronous).
+ * Not for production use.
+ */
+qmc_status qmc_probe_valu(double *fma_per_s, double *exp_per_s, double *sin_per_s, void *stream);
 qmc_status qmc_timing_reset(void);
 qmc_status qmc_timing_read(const char *name, double *ms, int64_t *launches);
 

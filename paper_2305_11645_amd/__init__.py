@@ -24,7 +24,7 @@ from .inputs import (DIGITAL_NET, DIGITAL_SHIFT, FP32, IID, G_COS, G_EXP, G_ID, 
 
 __all__ = ["Points", "Integrand_", "estimate", "estimate_grad", "reduced_matvec", "point_values",
            "point_matrix", "QMCEstimate", "QMCError", "QMCInvalid", "QMCUnsupported",
-           "QMCNoMemory", "QMCDeviceError", "EXPORTS", "timing"]
+           "QMCNoMemory", "QMCDeviceError", "EXPORTS", "timing", "probe_valu"]
 
 
 def _torch():
@@ -218,6 +218,14 @@ class _Lazy:
 
 
 QMCEstimate = _Lazy()
+
+
+def probe_valu():
+    """Measured VALU issue rates of the current GPU (lane operations per second):
+    {"fma": v_fma_f32, "exp": v_exp_f32 (+ one multiply), "sin": v_sin_f32}."""
+    f, e, s = ct.c_double(), ct.c_double(), ct.c_double()
+    check(load().qmc_probe_valu(ct.byref(f), ct.byref(e), ct.byref(s), _stream()))
+    return {"fma": f.value, "exp": e.value, "sin": s.value}
 
 
 class timing:

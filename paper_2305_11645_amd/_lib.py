@@ -17,7 +17,7 @@ EXPORTS = [
     "qmc_point_matrix", "qmc_workspace_size", "qmc_reduced_matvec", "qmc_estimate",
     "qmc_estimate_static",
     "qmc_estimate_grad", "qmc_status_string", "qmc_last_error", "qmc_timing_enable",
-    "qmc_timing_reset", "qmc_timing_read",
+    "qmc_timing_reset", "qmc_timing_read", "qmc_probe_valu",
 ]
 
 STATUS = {0: "QMC_OK", 1: "QMC_EINVAL", 2: "QMC_EUNSUPPORTED", 3: "QMC_ENOMEM", 4: "QMC_EDEVICE"}
@@ -45,6 +45,12 @@ def load() -> ct.CDLL:
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"libqmcred.so is not built ({LIB_PATH}); run "
                            "`python -m paper_2305_11645_amd.build` first")
+    # PyTorch's wheel carries its own HIP runtime under the same soname as the
+    # system one.  Importing torch first makes the dynamic linker resolve this
+    # library's HIP dependency to the copy torch already loaded, so the process
+    # runs one HIP runtime and torch's device pointers and streams are valid
+    # here; loaded the other way round, two runtimes would compete for the GPU.
+    import torch  # noqa: F401
     L = ct.CDLL(LIB_PATH)
     vp, i32, i64, sz = ct.c_void_p, ct.c_int32, ct.c_int64, ct.c_size_t
     L.qmc_points_init.argtypes = [ct.POINTER(vp), ct.POINTER(PointSpec)]
@@ -63,6 +69,7 @@ def load() -> ct.CDLL:
     L.qmc_last_error.restype = ct.c_char_p
     L.qmc_timing_enable.argtypes = [i32]
     L.qmc_timing_read.argtypes = [ct.c_char_p, ct.POINTER(ct.c_double), ct.POINTER(i64)]
+    L.qmc_probe_valu.argtypes = [ct.POINTER(ct.c_double)] * 3 + [vp]
     for name in EXPORTS:
         if name not in ("qmc_status_string", "qmc_last_error"):
             getattr(L, name).restype = ct.c_int32

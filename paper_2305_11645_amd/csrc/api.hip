@@ -312,6 +312,16 @@ qmc_status get_workspace(qmc_points p, size_t need, void *ws, size_t ws_bytes, h
 
 // ------------------------------------------------------------ timing hook
 namespace qmc {
+qmc_status record_error(qmc_status s, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return s;
+}
+
 LaunchTimer::LaunchTimer(const char *n, hipStream_t s) : name(n), st(s) {
   if (!g_tm_on) return;
   hipEvent_t e;
@@ -860,18 +870,19 @@ static qmc_status estimate_impl(qmc_points p, const float *A, int32_t t, int64_t
     QMC_HIP(launch_reduce(wk.ppartial, nr, blocks, 1.0 / (double)G.N, Q, st), "reduce launch");
     if (!grad) return QMC_OK;
   }
-  // adjoint: G_ki = h'(u_k) g'(y_ki) / (N t)
+  // adjoint: G_ki = h'(u_k) g'(y_ki) / (N t); the kernels work with
+  // G'_ki = h'(u_k) g'_unit(y_ki) and the combination applies the factor
   LeafOut g{};
   g.partial = wk.partial;
   g.dApart = wk.dlow;
   g.Sroot = wk.S;
   g.hd = sep ? nullptr : wk.hd;
-  g.gscale = inv_nt;
   QMC_HIP(launch_leaf(G, kModeGrad, *f, wk.tables, wk.U, nr, 0, A, t, lda, ldu, lg, g, st), "adjoint leaf launch");
   if (sep) QMC_HIP(launch_reduce(wk.partial, nr, (int64_t)lg.gx * lg.gy, inv_nt, Q, st), "reduce launch");
   QMC_HIP(launch_fold(G, nr, wk.S, t, ldu, st), "fold launch");
   QMC_HIP(launch_levels_adj(G, prec, wk.tables, nr, wk.S, t, ldu, wk.dup, st), "adjoint levels launch");
-  QMC_HIP(launch_combine(G, wk.dlow, lg.gx, tct, wk.dup, nr, t, ldu, dA, st), "combine launch");
+  QMC_HIP(launch_combine(G, wk.dlow, lg.gx, tct, wk.dup, nr, t, ldu, inv_nt * g_der_factor(*f), dA, st),
+          "combine launch");
   return QMC_OK;
 }
 

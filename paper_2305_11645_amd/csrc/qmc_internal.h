@@ -113,6 +113,20 @@ __device__ __forceinline__ float g_der(float ys, float c) {
   return 1.0f;
 }
 
+// The per-point part of g'(y) from the scaled argument y': sin (cos: g' is
+// -sin), 2^{y'} (exp(c y): g' is c exp(c y)) or 1; the constant factor
+// g_der_factor (-1, c or 1) multiplies the summed adjoint instead.  NEAR: the
+// argument is known to lie inside v_sin's input domain (+-256 revolutions).
+template <int GF, bool NEAR>
+__device__ __forceinline__ float g_der_unit(float ys) {
+  if (GF == QMC_G_COS) return __builtin_amdgcn_sinf(NEAR ? ys : __builtin_amdgcn_fractf(ys));
+  if (GF == QMC_G_EXP) return __builtin_amdgcn_exp2f(ys);
+  return 1.0f;
+}
+inline double g_der_factor(const qmc_integrand &f) {
+  return f.g == QMC_G_COS ? -1.0 : f.g == QMC_G_EXP ? f.c : 1.0;
+}
+
 // Per-call timing hook (no-op unless enabled).
 struct LaunchTimer {
   const char *name;
@@ -121,6 +135,9 @@ struct LaunchTimer {
   LaunchTimer(const char *n, hipStream_t s);
   ~LaunchTimer();
 };
+
+// Records the detail returned by qmc_last_error() and passes the status through.
+qmc_status record_error(qmc_status s, const char *fmt, ...);
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
@@ -184,8 +201,6 @@ struct LeafArgs {
   int64_t tstride, ustride, lda, ldu, ldy;
   uint32_t ldu32;               // ldu (< 2^32)
   float sigma;                  // y' = sigma y: 1/(2 pi) for cos, c log2(e) for exp
-  float gc;                     // parameter c of exp(c y)
-  double gscale;                // adjoint factor
 };
 
 // sigma for an integrand and leaf mode
@@ -196,10 +211,11 @@ struct LeafOut {
   float *ppart;        // kModePoint: [nr][tct][N] per-point sums over a column tile
   float *Y;            // kModeStoreY
   int64_t ldy;
+  // kModeGrad works with the unscaled sensitivities G'_ki = h'(u_k) g'_unit(y_ki)
+  // (g_der_unit); the factor g_der_factor / (N t) is applied by launch_combine.
   float *dApart;       // kModeGrad: [nr][gx][tct][jlow][64] lower-level dA partials
-  float *Sroot;        // kModeGrad: [nr][nsub][ldu] subtree-root sums of G
+  float *Sroot;        // kModeGrad: [nr][2 nsub][ldu] subtree-root sums of G' (pyramid base)
   const float *hd;     // kModeGrad, non-separable h: [nr][N] per-point factor h'(u)
-  double gscale;       // kModeGrad: factor of g' (1/(N t) for separable h)
 };
 
 struct LeafPlan {
@@ -286,10 +302,10 @@ hipError_t launch_point_h(const Geometry &G, const qmc_integrand &f, const float
                           double hscale, hipStream_t st);
 int64_t point_h_blocks(const Geometry &G);
 
-// dA[r][j][i] = sum of the lower partials (rows j < jlow) or of the upper
-// partials (rows of the upper levels), FP64 accumulation, FP32 result.
+// dA[r][j][i] = scale x (sum of the lower partials (rows j < jlow) or of the
+// upper partials (rows of the upper levels)), FP64 accumulation, FP32 result.
 hipError_t launch_combine(const Geometry &G, const float *dApart_low, int gx, int tct,
-                          const float *dApart_up, int nr, int t, int64_t ldu, float *dA,
+                          const float *dApart_up, int nr, int t, int64_t ldu, double scale, float *dA,
                           hipStream_t st);
 
 }  // namespace qmc

@@ -124,6 +124,7 @@ hipError_t launch_fold(const Geometry &G, int nr, float *S, int t, int64_t ldu, 
 
 struct CombineArgs {
   Geometry G;
+  double scale;
   int32_t gx, tct, t, nr;
   int64_t ldu, up_rs;
   int64_t poff[kMaxLevels];    // per upper level u: offset of its partial blocks
@@ -155,16 +156,17 @@ __global__ __launch_bounds__(256) void combine_kernel(CombineArgs a, const float
         for (int c = 0; c < a.kchunks[u]; ++c) acc += (double)p[(int64_t)c * L.tau * a.ldu];
       }
     }
-    dA[((int64_t)r * G.s + j) * a.t + col] = (float)acc;
+    dA[((int64_t)r * G.s + j) * a.t + col] = (float)(a.scale * acc);
   }
 }
 
 hipError_t launch_combine(const Geometry &G, const float *dApart_low, int gx, int tct,
-                          const float *dApart_up, int nr, int t, int64_t ldu, float *dA,
+                          const float *dApart_up, int nr, int t, int64_t ldu, double scale, float *dA,
                           hipStream_t st) {
   LaunchTimer tm("combine", st);
   CombineArgs a;
   a.G = G;
+  a.scale = scale;
   a.gx = gx;
   a.tct = tct;
   a.t = t;

@@ -247,3 +247,18 @@ def test_timing_api_on_host():
     q.timing.reset()
     assert q.timing.read("leaf") == (0.0, 0)
     q.timing.enable(False)
+
+
+def test_one_hip_runtime_when_the_library_loads_first():
+    """PyTorch's wheel carries its own HIP runtime under the system soname.
+    Loading libqmcred before touching torch must still leave one HIP runtime in
+    the process (torch's), or torch would find no GPU after the library took it."""
+    import subprocess
+    import sys
+    code = ("import paper_2305_11645_amd as q; q.load()\n"
+            "libs = {l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}\n"
+            "print(len(libs)); print(sorted(libs))\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.splitlines()[0] == "1", out.stdout
