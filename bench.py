@@ -58,7 +58,7 @@ def leaf_traffic(config: int, op: str = "estimate", kernel: str = "leaf_kernel")
             k, v = ln.strip().split(":", 1)
             fields[k.strip()] = v.strip()
     csrc = os.path.join(ROOT, "paper_2305_11645_amd", "csrc")
-    sources = fields.get("kernel_sources", "leaf.hip qmc_internal.h").split()
+    sources = fields.get("kernel_sources", "leaf.hip leaf_common.h qmc_internal.h").split()
     sha = hashlib.sha256(b"".join(open(os.path.join(csrc, f), "rb").read() for f in sources)).hexdigest()[:16]
     if fields.get("kernel_source_sha256_16") != sha or "hbm_bytes_per_dispatch" not in fields:
         return None

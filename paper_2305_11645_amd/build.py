@@ -17,7 +17,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libqmcred.so")
-SOURCES = ["api.hip", "tables.hip", "levels.hip", "leaf.hip", "reduce.hip", "alg4.hip", "probe.hip"]
+SOURCES = ["api.hip", "tables.hip", "levels.hip", "leaf.hip", "adjoint.hip", "reduce.hip", "alg4.hip", "probe.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

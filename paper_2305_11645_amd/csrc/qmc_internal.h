@@ -230,6 +230,13 @@ LeafPlan leaf_plan(const Geometry &G, int t, int nr, int mode, int gf);
 // compute units), cached; 0 when the query fails.
 int64_t resident_workgroups(const void *fn, int threads, size_t lds);
 
+// The register form of the gradient mode (adjoint.hip): whether it applies
+// (every lower level I holds at most 2^I coordinates) and its kernel for an
+// integrand g and a per-point factor h' (hd).  It takes the LeafArgs of
+// launch_leaf and (tables, U, A, partial, dApart, Sroot, hd).
+bool grad_reg_ok(const Geometry &G);
+const void *grad_fn(const Geometry &G, int gf, bool hd);
+
 hipError_t launch_leaf(const Geometry &G, int mode, const qmc_integrand &f, const float *tables,
                        const float *U, int nr, int r0, const float *A, int t, int64_t lda,
                        int64_t ldu, const LeafPlan &lp, const LeafOut &o, hipStream_t st);
