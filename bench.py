@@ -114,6 +114,20 @@ def measured_valu():
     return _VALU_RATES
 
 
+_MFMA_RATES = None
+
+
+def measured_mfma():
+    """The matrix-core rates measured on this GPU (qmc_probe_mfma), in TFLOP/s."""
+    global _MFMA_RATES
+    if _MFMA_RATES is None:
+        import paper_2305_11645_amd as q
+        q.probe_mfma()  # the first pass runs while the clocks ramp up
+        r = q.probe_mfma()
+        _MFMA_RATES = {k: round(v / 1e12, 1) for k, v in r.items()}
+    return _MFMA_RATES
+
+
 def alu_roofline(kernel: str, achieved: float, slots: float, avg_ms: float, traffic):
     """The roofline object of an ALU-bound kernel: achieved FMA-equivalent
     TFLOP/s against the unpacked FP32 peak, with the packed-peak fraction and the
@@ -318,7 +332,7 @@ def bench_grad(args, wl) -> int:
         roofline = {"bound": "mfma", "kernel": "alg4_adj_kernel", "achieved": round(achieved, 3), "peak": peak,
                     "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
                     "traffic": leaf_traffic(args.config, "grad", kernel="alg4_adj_kernel"),
-                    "algorithmic_flops": mf}
+                    "algorithmic_flops": mf, "measured_rates_TFLOP_per_s": measured_mfma()}
     elif "leaf_grad" in kern:
         # the tree path: the gradient-mode leaf pass is the dominant kernel
         lms = kern["leaf_grad"]["ms_per_step"] * args.steps / kern["leaf_grad"]["launches"]
@@ -482,7 +496,7 @@ def bench_estimate(args, wl) -> int:
         roofline = {"bound": "mfma", "kernel": "alg4_kernel", "achieved": round(achieved, 3),
                     "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
                     "traffic": leaf_traffic(args.config, kernel="alg4_kernel"), "avg_ms": round(leaf_ms, 5),
-                    "algorithmic_flops": mf}
+                    "algorithmic_flops": mf, "measured_rates_TFLOP_per_s": measured_mfma()}
     else:
         slots = leaf_algorithmic_slots(wl, pts.split_level)
         achieved = 2 * slots / (leaf_ms * 1e-3) / 1e12

@@ -282,6 +282,13 @@ qmc_status qmc_timing_enable(int32_t on);
  * Not for production use.
  */
 qmc_status qmc_probe_valu(double *fma_per_s, double *exp_per_s, double *sin_per_s, void *stream);
+/*
+ * Measured matrix-core rates of the current device in flop/s, for the roofline
+ * of the grouped products: v_mfma_f32_32x32x2_f32 and v_mfma_f32_16x16x4_f32
+ * (FP32) and v_mfma_f32_32x32x16_bf16, four independent accumulators per wave.
+ * Same conditions as qmc_probe_valu.
+ */
+qmc_status qmc_probe_mfma(double *f32_32x32x2, double *f32_16x16x4, double *bf16_32x32x16, void *stream);
 qmc_status qmc_timing_reset(void);
 qmc_status qmc_timing_read(const char *name, double *ms, int64_t *launches);
 

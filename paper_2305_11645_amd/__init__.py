@@ -24,7 +24,7 @@ from .inputs import (DIGITAL_NET, DIGITAL_SHIFT, FP32, IID, G_COS, G_EXP, G_ID, 
 
 __all__ = ["Points", "Integrand_", "estimate", "estimate_grad", "reduced_matvec", "point_values",
            "point_matrix", "QMCEstimate", "QMCError", "QMCInvalid", "QMCUnsupported",
-           "QMCNoMemory", "QMCDeviceError", "EXPORTS", "timing", "probe_valu"]
+           "QMCNoMemory", "QMCDeviceError", "EXPORTS", "timing", "probe_valu", "probe_mfma"]
 
 
 def _torch():
@@ -226,6 +226,14 @@ def probe_valu():
     f, e, s = ct.c_double(), ct.c_double(), ct.c_double()
     check(load().qmc_probe_valu(ct.byref(f), ct.byref(e), ct.byref(s), _stream()))
     return {"fma": f.value, "exp": e.value, "sin": s.value}
+
+
+def probe_mfma():
+    """Measured matrix-core rates of the current GPU (flop/s): {"f32_32x32x2",
+    "f32_16x16x4", "bf16_32x32x16"}."""
+    a, b, c = ct.c_double(), ct.c_double(), ct.c_double()
+    check(load().qmc_probe_mfma(ct.byref(a), ct.byref(b), ct.byref(c), _stream()))
+    return {"f32_32x32x2": a.value, "f32_16x16x4": b.value, "bf16_32x32x16": c.value}
 
 
 class timing:

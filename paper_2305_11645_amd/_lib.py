@@ -17,7 +17,7 @@ EXPORTS = [
     "qmc_point_matrix", "qmc_workspace_size", "qmc_reduced_matvec", "qmc_estimate",
     "qmc_estimate_static",
     "qmc_estimate_grad", "qmc_status_string", "qmc_last_error", "qmc_timing_enable",
-    "qmc_timing_reset", "qmc_timing_read", "qmc_probe_valu",
+    "qmc_timing_reset", "qmc_timing_read", "qmc_probe_valu", "qmc_probe_mfma",
 ]
 
 STATUS = {0: "QMC_OK", 1: "QMC_EINVAL", 2: "QMC_EUNSUPPORTED", 3: "QMC_ENOMEM", 4: "QMC_EDEVICE"}
@@ -70,6 +70,7 @@ def load() -> ct.CDLL:
     L.qmc_timing_enable.argtypes = [i32]
     L.qmc_timing_read.argtypes = [ct.c_char_p, ct.POINTER(ct.c_double), ct.POINTER(i64)]
     L.qmc_probe_valu.argtypes = [ct.POINTER(ct.c_double)] * 3 + [vp]
+    L.qmc_probe_mfma.argtypes = [ct.POINTER(ct.c_double)] * 3 + [vp]
     for name in EXPORTS:
         if name not in ("qmc_status_string", "qmc_last_error"):
             getattr(L, name).restype = ct.c_int32

@@ -213,6 +213,31 @@ def test_estimate_library_workspace():
     assert torch.equal(Q, q.estimate(pts, A, f))
 
 
+def test_workspace_allocation_failure_leaves_the_point_set_usable(monkeypatch):
+    """QMC_FAULT_INJECT=alloc makes the library's own workspace allocation fail:
+    the call returns QMC_ENOMEM before launching anything (Q untouched), and
+    the next call on the same point set succeeds with the usual result."""
+    import ctypes as ct
+    torch = torch_cuda()
+    wl = small(I.LATTICE, I.RANDOM_SHIFT, R=2)
+    pts = q.Points.from_workload(wl)
+    A = to_dev(wl.A, torch)
+    f = q.Integrand_.of(wl)
+    L = q.load()
+    st = ct.c_void_p(torch.cuda.current_stream().cuda_stream)
+    Q = torch.full((2,), 5.0, dtype=torch.float64, device="cuda")
+    monkeypatch.setenv("QMC_FAULT_INJECT", "alloc")
+    rc = L.qmc_estimate(pts.handle, ct.c_void_p(A.data_ptr()), wl.t, wl.t, ct.byref(f.c_struct()), 0,
+                        ct.c_void_p(Q.data_ptr()), None, 0, st)
+    assert rc == 3 and b"fault injection" in L.qmc_last_error()
+    torch.cuda.synchronize()
+    assert torch.all(Q == 5.0)
+    monkeypatch.delenv("QMC_FAULT_INJECT")
+    q._lib.check(L.qmc_estimate(pts.handle, ct.c_void_p(A.data_ptr()), wl.t, wl.t, ct.byref(f.c_struct()), 0,
+                                ct.c_void_p(Q.data_ptr()), None, 0, st))
+    assert torch.equal(Q, q.estimate(pts, A, f))
+
+
 # ------------------------------------------------------------------ gradient
 
 @pytest.mark.parametrize("kind", KINDS)
