@@ -157,7 +157,7 @@ def alg4(wl, r: int, A: np.ndarray | None = None, i0: int = 0, i1: int | None = 
 def output_values(wl, r: int, j: int) -> np.ndarray:
     """Values of coordinate j indexed by the integer of its reduced output digits."""
     sp = Spec(wl)
-    n = 1 << int(wl.nbits()[j])
+    n = wl.b ** int(wl.nbits()[j])
     out = np.empty(n, dtype=np.float64)
     assert lib().qo_output_values(ct.byref(sp.c), r, j, _dp(out)) == 0
     return out

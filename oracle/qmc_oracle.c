@@ -35,7 +35,8 @@
  *     adds the K base-b digits of an integer delta < b^K (b^K <= 2^52, most
  *     significant first) digit by digit mod b and takes the midpoint of the
  *     rest: x = (U + 1/2) / b^K (for b = 2, K = 52 and x = (2U + 1) 2^-53);
- *     nets in base b > 2 must be periodic after reduction;
+ *     a net that is not periodic after reduction takes Algorithm 4 in any
+ *     prime base, its values indexed by the integer of the output digits;
  *   - the inverse normal map is Wichura's algorithm AS241 (PPND16);
  *   - the integrand is f(y) = h(t^-1 sum_i g(y_i)) with g in {y, cos y,
  *     exp(c y)} and h in {u, max(0, u - K)}; h'(K) is taken as 0;
@@ -308,15 +309,14 @@ static uint64_t reduced_int(const qo_spec *sp, int j, uint64_t rho) {
 
 static int net_is_periodic(const qo_spec *sp);
 
-/* The bases taken here: b = 2 for every kind; a prime b > 2 for every kind
- * except nets that are not periodic after reduction (and reduced Monte Carlo
+/* The bases taken here: every prime b, for every kind (reduced Monte Carlo
  * takes no shift in any base). */
 static int base_supported(const qo_spec *sp) {
     if (sp->b == 2) return 1;
     if (sp->b < 2) return 0;
     for (int d = 2; d * d <= sp->b; ++d)
         if (sp->b % d == 0) return 0;
-    return sp->kind != QO_DIGITAL_NET || net_is_periodic(sp);
+    return 1;
 }
 
 /* Distinct values X_j[rho], rho < n_j, of coordinate j for shift r (FP64). */
@@ -477,13 +477,20 @@ static int net_is_periodic(const qo_spec *sp) {
 int qo_net_is_periodic(const qo_spec *sp) { return net_is_periodic(sp); }
 
 /* Values X_j[c] of coordinate j indexed by the integer c of the reduced output
- * digits (x = c / 2^nb before shift and map), c < n_j: the n_j possible values
+ * digits (x = c / b^nb before shift and map), c < n_j: the n_j possible values
  * of Section 3 (after eq. reduced_genmat_net2). */
 int qo_output_values(const qo_spec *sp, int r, int j, double *out) {
     int nb = nbits_of(sp, j);
-    uint64_t n = UINT64_C(1) << nb;
+    uint64_t n = n_of(sp, j);
     for (uint64_t c = 0; c < n; ++c) out[c] = shift_and_map(sp, r, j, c, nb);
     return 0;
+}
+
+/* The integer of the reduced output digits of point n in coordinate j: the
+ * nb leading base-b digits of the unreduced value times b^m. */
+static uint64_t output_int(const qo_spec *sp, int j, uint64_t n) {
+    int nb = nbits_of(sp, j);
+    return unreduced_int_over_N(sp, j, n) / ipow((uint64_t)sp->b, sp->m - nb);
 }
 
 /*
@@ -495,17 +502,17 @@ int qo_output_values(const qo_spec *sp, int r, int j, double *out) {
  */
 int qo_alg4(const qo_spec *sp, int r, const double *A, int t, int i0, int i1,
             double *P, int64_t *nmadd) {
+    if (!base_supported(sp)) return 3;
     int tb = i1 - i0;
-    int64_t N = (int64_t)1 << sp->m;
+    int64_t N = N_of(sp);
     for (int64_t e = 0; e < N * tb; ++e) P[e] = 0.0;
-    double *v = (double *)malloc(sizeof(double) * ((size_t)1 << sp->m));
-    double *c = (double *)malloc(sizeof(double) * ((size_t)1 << sp->m) * tb);
+    double *v = (double *)malloc(sizeof(double) * (size_t)N);
+    double *c = (double *)malloc(sizeof(double) * (size_t)N * tb);
     if (!v || !c) { free(v); free(c); return 1; }
     int64_t count = 0;
     for (int j = sp->s - 1; j >= 0; --j) {
         if (column_is_zero(sp, j)) continue;
-        int nb = nbits_of(sp, j);
-        int64_t nj = (int64_t)1 << nb;
+        int64_t nj = (int64_t)n_of(sp, j);
         qo_output_values(sp, r, j, v);
         const double *aj = A + (size_t)j * t + i0;
         for (int64_t k = 0; k < nj; ++k)
@@ -513,7 +520,7 @@ int qo_alg4(const qo_spec *sp, int r, const double *A, int t, int i0, int i1,
         if (sp->w[j] < sp->m) count += nj * tb;
 #pragma omp parallel for schedule(static)
         for (int64_t n = 0; n < N; ++n) {
-            uint64_t k = unreduced_int_over_N(sp, j, (uint64_t)n) >> (sp->m - nb);
+            uint64_t k = output_int(sp, j, (uint64_t)n);
             for (int i = 0; i < tb; ++i) P[n * tb + i] = P[n * tb + i] + c[k * tb + i];
         }
     }
@@ -647,16 +654,15 @@ int qo_estimate_grad(const qo_spec *sp, const double *A, int t, const qo_integra
                 for (int i = 0; i < w; ++i) P[k * w + i] = hk * g_der(f, P[k * w + i]);
             }
             if (!periodic) {
-                /* Algorithm 4 transposed (a net that is not periodic, base 2):
+                /* Algorithm 4 transposed (a net that is not periodic):
                  * point n contributes to the value X_j[c] with c = floor(y_{n,j} n_j),
                  * the integer of its reduced output digits, so
                  * dA_j = sum_c X_j[c] S_j[c],  S_j[c] = sum of G_n over those n */
                 for (int j = 0; j < s; ++j) {
-                    int nb = nbits_of(sp, j);
-                    int64_t nj = (int64_t)1 << nb;
+                    int64_t nj = (int64_t)n_of(sp, j);
                     for (int64_t e = 0; e < nj * w; ++e) S[e] = 0.0;
                     for (int64_t n = 0; n < N; ++n) {
-                        uint64_t c = unreduced_int_over_N(sp, j, (uint64_t)n) >> (sp->m - nb);
+                        uint64_t c = output_int(sp, j, (uint64_t)n);
                         for (int i = 0; i < w; ++i) S[c * w + i] = S[c * w + i] + P[n * w + i];
                     }
                     qo_output_values(sp, r, j, v);

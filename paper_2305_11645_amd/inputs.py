@@ -206,12 +206,19 @@ def tridiag_cholesky_T(s: int, diag: float = 0.4, off: float = 0.2) -> np.ndarra
     return np.ascontiguousarray(np.linalg.cholesky(Sig).T)
 
 
-def draw_net_upper(rng: np.random.Generator, s: int, m: int) -> np.ndarray:
-    """Random upper-triangular generating matrices over F_2 with unit diagonal
-    (the shape of Sobol' matrices): C_{p,q} = 0 for p > q, one on the diagonal,
-    fair bits above it.  Column words as in draw_net_lower.  After the row
-    reduction the points still depend on every digit of k (not periodic), so
-    products over them need Algorithm 4."""
+def draw_net_upper(rng: np.random.Generator, s: int, m: int, b: int = 2) -> np.ndarray:
+    """Random upper-triangular generating matrices over F_b with a nonzero
+    diagonal (the shape of Sobol' matrices; F_2: unit diagonal): C_{p,q} = 0
+    for p > q, uniform digits above the diagonal.  Column words as in
+    draw_net_lower.  After the row reduction the points still depend on every
+    digit of k (not periodic), so products over them need Algorithm 4."""
+    if b != 2:
+        words = np.zeros(s * m, dtype=np.uint64)
+        for j in range(s):
+            for q in range(m):
+                col = [int(rng.integers(0, b)) for _ in range(q)] + [int(rng.integers(1, b))] + [0] * (m - q - 1)
+                words[j * m + q] = np.uint64(sum(c * b ** p for p, c in enumerate(col)))
+        return words
     words = np.zeros(s * m, dtype=np.uint64)
     for j in range(s):
         bits = rng.integers(0, 2, size=(m, m))
@@ -393,9 +400,7 @@ def make_custom(*, kind: int, m: int, s: int, t: int, w: np.ndarray, rand: int =
     elif kind == IID:
         gen = np.ones(s, dtype=np.uint64)  # unused
     elif net == "upper":
-        if b != 2:
-            raise ValueError("upper-triangular nets are drawn in base 2 only")
-        gen = draw_net_upper(rng, s, m)
+        gen = draw_net_upper(rng, s, m, b)
     else:
         gen = draw_net_lower(rng, s, m, b)
     A64 = rng.standard_normal((s, t)) * A_scale

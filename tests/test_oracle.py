@@ -769,19 +769,102 @@ def test_base_b_digital_shift_linear_integrand_exact(oracle_lib, b, m, kind):
         assert abs(Q[r] - ref) <= 1e-13 * max(1.0, abs(ref))
 
 
-def test_base_b_net_not_periodic_is_refused(oracle_lib):
-    """A base-3 net whose reduced matrix has a nonzero entry in a column past
-    n_j is not periodic; the oracle takes base b > 2 nets only when periodic."""
+UPPER_B = [(3, 5), (5, 3), (7, 3)]   # (b, m): N = 243, 125, 343
+
+
+def upper_net_b(b, m, s=9, t=5, R=2, rand=I.DIGITAL_SHIFT, mp=I.MAP_CENTER, seed=9, g=I.G_COS, h=I.H_ID, K=0.0):
+    R = R if rand != I.NO_SHIFT else 1
+    return I.make_custom(kind=I.DIGITAL_NET, m=m, s=s, t=t, w=I.w_logb(s, m + 1, b), rand=rand, R=R, map=mp,
+                         g=g, h=h, K=K, seed=seed, net="upper", b=b)
+
+
+@pytest.mark.parametrize("b,m", UPPER_B)
+def test_base_b_net_periodicity_detection(oracle_lib, b, m):
+    """Over F_b as over F_2: a lower-triangular C^{(j)} leaves zero columns past
+    n_j after the row reduction (periodic), an upper-triangular one does not;
+    a single entry in a column past n_j within the first n_j rows breaks it."""
     import dataclasses
     O = oracle_lib
-    wl = I.make_custom(kind=I.DIGITAL_NET, m=3, s=2, t=2, w=[0, 1], seed=2, b=3)
+    assert not O.net_is_periodic(upper_net_b(b, m))
+    wl = I.make_custom(kind=I.DIGITAL_NET, m=3, s=2, t=2, w=[0, 1], seed=2, b=b)
     assert O.net_is_periodic(wl)
     gen = wl.gen.copy()
     gen[1 * 3 + 2] = np.uint64(1)  # C^{(2)}_{1,3} = 1: row 1 <= e = 2 in column 3 > e
-    bad = dataclasses.replace(wl, gen=gen)
-    assert not O.net_is_periodic(bad)
-    with pytest.raises(AssertionError):
-        O.point_values(bad, 0, 0)
+    assert not O.net_is_periodic(dataclasses.replace(wl, gen=gen))
+
+
+@pytest.mark.parametrize("b,m", UPPER_B)
+@pytest.mark.parametrize("rand", RANDS)
+def test_base_b_alg4_output_values_match_points(oracle_lib, b, m, rand):
+    """Section 3 over F_b: coordinate j of a net that is not periodic takes only
+    the n_j values c / b^{n_j} (then shifted and mapped), point n the one with
+    c the integer of its reduced output digits y_p = sum_q C_{p,q} n_q mod b,
+    computed here from brute force's explicit digit vectors and matrices."""
+    O = oracle_lib
+    wl = upper_net_b(b, m, rand=rand, mp=I.MAP_ID if rand == I.NO_SHIFT else I.MAP_CENTER)
+    for r in range(wl.R):
+        X = brute.point_matrix(wl, r)
+        for j in range(wl.s):
+            vals = O.output_values(wl, r, j)
+            nb = wl.m - min(int(wl.w[j]), wl.m)
+            assert len(vals) == b ** nb
+            C = brute.reduced_net_matrix(wl, j)
+            for n in range(wl.N):
+                d = brute.digits(n, wl.m, b)
+                y = [sum(C[p][q] * d[q] for q in range(wl.m)) % b for p in range(wl.m)]
+                c = sum(y[p] * b ** (nb - 1 - p) for p in range(nb))
+                assert vals[c] == X[n, j], (r, j, n)
+
+
+@pytest.mark.parametrize("b,m", UPPER_B)
+def test_base_b_alg4_matches_dense(oracle_lib, b, m):
+    """Algorithm 4 over F_b equals the dense product X A, X built digit by digit
+    by brute force, with t sum_{j <= s*} n_j multiplications."""
+    O = oracle_lib
+    wl = upper_net_b(b, m, s=11, t=6, mp=I.MAP_INVNORM)
+    A = wl.A.astype(np.float64)
+    nmul = wl.t * sum(b ** int(n) for n, w in zip(wl.nbits(), wl.w) if w < wl.m)
+    for r in range(wl.R):
+        P, cnt = O.alg4(wl, r)
+        Yd = brute.point_matrix(wl, r) @ A
+        assert np.linalg.norm(P - Yd) <= 1e-13 * np.linalg.norm(Yd)
+        assert cnt == nmul
+        Yu = O.point_matrix_unreduced(wl, r) @ A
+        assert np.linalg.norm(P - Yu) <= 1e-13 * np.linalg.norm(Yu)
+
+
+@pytest.mark.parametrize("b,m", UPPER_B)
+def test_base_b_alg4_estimate_and_gradient_match_definition(oracle_lib, b, m):
+    """For a net over F_b that is not periodic, the oracle's estimate equals
+    eq. QMC-rule on the brute-force point matrix and its dQ/dA equals X^T G."""
+    O = oracle_lib
+    wl = upper_net_b(b, m, s=10, t=5, mp=I.MAP_INVNORM, g=I.G_EXP, h=I.H_CALL, K=1.0)
+    wl.c = 0.3
+    assert not O.net_is_periodic(wl)
+    A = wl.A.astype(np.float64)
+    Q, dA = O.estimate_grad(wl)
+    for r in range(wl.R):
+        X = brute.point_matrix(wl, r)
+        u = np.mean(np.exp(wl.c * (X @ A)), axis=1)
+        ref = float(np.mean(np.maximum(u - wl.K, 0.0)))
+        assert abs(Q[r] - ref) <= 1e-13 * max(abs(ref), 1e-300)
+        gref = _dense_grad(wl, A, X, r)
+        assert np.linalg.norm(dA[r] - gref) <= 1e-12 * np.linalg.norm(gref)
+
+
+def test_base_b_alg4_gradient_finite_differences(oracle_lib):
+    """Central differences of the oracle estimate of a base-3 net that is not
+    periodic agree with <dA, V> along a random direction V."""
+    O = oracle_lib
+    wl = upper_net_b(3, 5, s=10, t=4, R=1, mp=I.MAP_CENTER, g=I.G_EXP, h=I.H_ID)
+    wl.c = 0.4
+    A = wl.A.astype(np.float64)
+    _, dA = O.estimate_grad(wl, A=A)
+    V = np.random.default_rng(6).standard_normal(A.shape)
+    eps = 1e-5
+    qp, _ = O.estimate(wl, A=A + eps * V)
+    qm, _ = O.estimate(wl, A=A - eps * V)
+    assert abs((qp[0] - qm[0]) / (2 * eps) - float(np.sum(dA[0] * V))) <= 1e-8
 
 
 @pytest.mark.parametrize("g,h", [(I.G_COS, I.H_ID), (I.G_EXP, I.H_CALL)])
