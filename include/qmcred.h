@@ -19,8 +19,8 @@
  * Conventions for every call:
  *   - Indices are 0-based: coordinate j = 0..s-1 is the paper's j+1.
  *   - b is a prime, 1 <= m <= 24 and N = b^m <= 2^24 (QMC_EUNSUPPORTED
- *     otherwise).  In a base b > 2 every kind is supported except nets that
- *     are not periodic after reduction (Algorithm 4 is built for b = 2).
+ *     otherwise).  Every kind is supported in every prime base; a net over
+ *     F_b, b > 2, that is not periodic after reduction needs N s <= 2^29.
  *   - Matrices are row-major FP32 with an explicit leading dimension.
  *   - "device" pointers are HIP device memory on the device that was current
  *     when the point set was created; "host" pointers are ordinary memory.
@@ -159,9 +159,12 @@ typedef struct qmc_points_s *qmc_points;
  * decreasing, a generator outside its allowed set, shift outside [0,1) or
  * >= 2^52, R < 1, INVNORM without a shift, QMC_IID with a shift, without
  * samples or with a sample outside [0,1) ((0,1) under INVNORM);
- * EUNSUPPORTED: m outside [1, 24], b^m > 2^24, a net in base b > 2 that is
- * not periodic after reduction), plans the levels and uploads generators,
- * shifts and samples.  A base b > 2 is evaluated like Algorithm 4: the n_j
+ * EUNSUPPORTED: m outside [1, 24], b^m > 2^24, a net over F_b, b > 2, that is
+ * not periodic after reduction with N s > 2^29), plans the levels and uploads
+ * generators, shifts and samples.  A net that is not periodic after
+ * reduction (any prime b) takes Algorithm 4: its values are tabulated by the
+ * integer of their reduced output digits; over F_b, b > 2, the index of every
+ * point and coordinate is tabulated once here (N s words).  A base b > 2 is evaluated like Algorithm 4: the n_j
  * values of every coordinate (c / b^e, one correctly rounded FP64 division
  * before shift and map; Section 4 for samples) are tabulated, and point k
  * reads value k mod n_j.

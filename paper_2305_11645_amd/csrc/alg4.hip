@@ -78,7 +78,8 @@ __device__ __forceinline__ float load_f32(__amdgpu_buffer_rsrc_t r, uint32_t byt
 }
 
 // IDX: how a point's value index combines the tile word and the lane word
-// (0: XOR, nets that are not periodic; 1: add, base b > 2).
+// (0: XOR, nets that are not periodic over F_2; 1: add, base b > 2; 2: one
+// word per point and coordinate, nets over F_b, b > 2, that are not periodic).
 //
 // Work items are (64-point tile tn, 256-column tile ct, randomisation rl),
 // item = tn + ntiles (ct + tct rl).  A workgroup takes a contiguous range of
@@ -164,8 +165,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC == QMC
 #pragma unroll
     for (int q = 0; q < KPW; ++q) {
       const int j = a.j0 + min(c.k0 + KPW * w + q, a.sc - 1);
-      yl[q] = D.ylo[(int64_t)j * 64 + lane];
-      yt[q] = ytile[j];
+      if (IDX == 2) {  // a word per point and coordinate
+        yl[q] = D.ylo[((int64_t)c.tn * a.s + j) * 64 + lane];
+        yt[q] = 0u;
+      } else {
+        yl[q] = D.ylo[(int64_t)j * 64 + lane];
+        yt[q] = ytile[j];
+      }
     }
   };
   // pad: a step past the stream (its rows of A read zero)
@@ -197,7 +203,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC == QMC
   auto row_of = [&](int i, int v) { return 32 * i + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3); };
   f32x16 acc[2][2];
   auto init_acc = [&](const Cursor &c) {
-    if (IDX && a.root) {
+    if (IDX == 1 && a.root) {
       const __amdgpu_buffer_rsrc_t rrs =
           raw_rsrc(a.root + (int64_t)c.rl * a.root_stride, (uint32_t)(a.nsplit * a.ldp * 4));
       const int base = (int)(((int64_t)c.tn * TM) % a.nsplit);
@@ -501,8 +507,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void a
     const int r = 32 * (int)((kp >> 5) & 1) + pl;
 #pragma unroll
     for (int q = 0; q < KPL; ++q) {
-      yl[q] = D.ylo[(int64_t)jq[q] * 64 + r];
-      yt[q] = D.ytile[tn * a.s + jq[q]];
+      if (IDX == 2) {
+        yl[q] = D.ylo[((int64_t)tn * a.s + jq[q]) * 64 + r];
+        yt[q] = 0u;
+      } else {
+        yl[q] = D.ylo[(int64_t)jq[q] * 64 + r];
+        yt[q] = D.ytile[tn * a.s + jq[q]];
+      }
     }
   };
   auto load_values = [&](int64_t kp, float (&b)[TK]) {
@@ -678,12 +689,17 @@ __global__ __launch_bounds__(256) void alg4_fold_kernel(const float *__restrict_
 }
 
 template <int PREC>
-static const void *adj_fn(bool add, int mi) {
-  if (add) return mi == 1 ? reinterpret_cast<const void *>(&alg4_adj_kernel<PREC, 1, 1>)
-                          : reinterpret_cast<const void *>(&alg4_adj_kernel<PREC, 1, 2>);
+static const void *adj_fn(int idx, int mi) {
+  if (idx == 2) return mi == 1 ? reinterpret_cast<const void *>(&alg4_adj_kernel<PREC, 2, 1>)
+                               : reinterpret_cast<const void *>(&alg4_adj_kernel<PREC, 2, 2>);
+  if (idx == 1) return mi == 1 ? reinterpret_cast<const void *>(&alg4_adj_kernel<PREC, 1, 1>)
+                               : reinterpret_cast<const void *>(&alg4_adj_kernel<PREC, 1, 2>);
   return mi == 1 ? reinterpret_cast<const void *>(&alg4_adj_kernel<PREC, 0, 1>)
                  : reinterpret_cast<const void *>(&alg4_adj_kernel<PREC, 0, 2>);
 }
+
+// The index mode of a point set (see IDX at alg4_kernel).
+static int index_mode(const Geometry &G) { return G.b == 2 ? 0 : G.nonperiodic ? 2 : 1; }
 
 template <int PREC, int MODE, int IDX, bool STREAM>
 static const void *fn_g(int gf) {
@@ -701,8 +717,9 @@ static const void *fn_m(int mode, int gf) {
 }
 
 template <int PREC>
-static const void *fn_p(bool add, bool stream, int mode, int gf) {
-  if (add) return stream ? fn_m<PREC, 1, true>(mode, gf) : fn_m<PREC, 1, false>(mode, gf);
+static const void *fn_p(int idx, bool stream, int mode, int gf) {
+  if (idx == 2) return stream ? fn_m<PREC, 2, true>(mode, gf) : fn_m<PREC, 2, false>(mode, gf);
+  if (idx == 1) return stream ? fn_m<PREC, 1, true>(mode, gf) : fn_m<PREC, 1, false>(mode, gf);
   return stream ? fn_m<PREC, 0, true>(mode, gf) : fn_m<PREC, 0, false>(mode, gf);
 }
 
@@ -713,13 +730,51 @@ static const void *fn_p(bool add, bool stream, int mode, int gf) {
 // dropped) and ytile[h][j] = aoff_j XOR y_j(64 h), each word restricted to its
 // first n_j digits; aoff_j is a multiple of n_j, so aoff_j XOR y = aoff_j + y
 // for y < n_j.  Base b > 2 (add = 1): ylo[j][r] = r mod n_j and ytile[h][j] =
-// aoff_j + (64 h mod n_j), whose sum stays below aoff_j + 2 n_j.
+// aoff_j + (64 h mod n_j), whose sum stays below aoff_j + 2 n_j.  A net over
+// F_b, b > 2, that is not periodic (full): its output digits have no such
+// split (digit-wise sums mod b carry no structure an integer add or XOR
+// reproduces), so ylo holds one word aoff_j + c per point and coordinate,
+// [tile][j][r], and ytile is unused.
+// Net over F_b (column words hold C_{p,q} as base-b digit p-1): the integer
+// c = sum_{p <= nb} y_p b^{nb-p} of the output digits y_p = sum_q C_{p,q} n_q
+// mod b of point n (all m digits of n; rows past nb of the reduced matrix are
+// zero).
+__device__ uint32_t net_output_int_b(const uint32_t *__restrict__ col, int m, int b, int nb, uint64_t n) {
+  uint32_t y[32];
+  for (int p = 0; p < nb; ++p) y[p] = 0u;
+  for (int q = 0; q < m; ++q) {
+    const uint32_t d = (uint32_t)(n % (uint32_t)b);
+    n /= (uint32_t)b;
+    if (!d) continue;
+    uint32_t wd = col[q];
+    for (int p = 0; p < nb; ++p) {
+      y[p] = (uint32_t)((y[p] + (uint64_t)(wd % (uint32_t)b) * d) % (uint32_t)b);
+      wd /= (uint32_t)b;
+    }
+  }
+  uint32_t c = 0;
+  for (int p = 0; p < nb; ++p) c = c * (uint32_t)b + y[p];
+  return c;
+}
+
 __global__ __launch_bounds__(256) void alg4_index_kernel(int32_t m, int32_t s, int32_t b, int64_t ntiles,
+                                                         int64_t N, bool full,
                                                          const uint32_t *__restrict__ gen,
                                                          const int32_t *__restrict__ nbj,
                                                          const uint32_t *__restrict__ aoff,
                                                          uint32_t *__restrict__ ylo,
                                                          uint32_t *__restrict__ ytile) {
+  if (full) {
+    // word [h][j][r]: aoff_j + the output integer of point min(64 h + r, N - 1)
+    const int64_t total = ntiles * s * 64;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+      const int64_t h = e / ((int64_t)s * 64);
+      const int j = (int)((e / 64) % s);
+      const int64_t n = min((int64_t)64 * h + (e & 63), N - 1);
+      ylo[e] = aoff[j] + net_output_int_b(gen + (int64_t)j * m, m, b, nbj[j], (uint64_t)n);
+    }
+    return;
+  }
   const int64_t nlo = (int64_t)64 * s, total = nlo + ntiles * s;
   const uint32_t lowmask = m >= 6 ? 63u : ((1u << m) - 1u);
   for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
@@ -749,7 +804,10 @@ __global__ __launch_bounds__(256) void alg4_index_kernel(int32_t m, int32_t s, i
 
 int64_t alg4_point_tiles(const Geometry &G) { return ceil_div(G.N, TM); }
 
-int64_t alg4_index_words(const Geometry &G) { return (64 + alg4_point_tiles(G)) * G.s; }
+int64_t alg4_index_words(const Geometry &G) {
+  if (G.b != 2 && G.nonperiodic) return alg4_point_tiles(G) * 64 * G.s;  // one word per point and coordinate
+  return (64 + alg4_point_tiles(G)) * G.s;
+}
 
 int alg4_col_tiles(int t) { return (int)ceil_div(t, TN); }
 
@@ -758,7 +816,7 @@ hipError_t launch_alg4_index(const Geometry &G, const uint32_t *gen, const int32
   const int64_t total = alg4_index_words(G);
   const int64_t blocks = std::min<int64_t>(ceil_div(total, 256), 65535);
   hipLaunchKernelGGL(alg4_index_kernel, dim3((unsigned)blocks), dim3(256), 0, st, G.m, G.s, G.b,
-                     alg4_point_tiles(G), gen, nbj, aoff, ylo, ytile);
+                     alg4_point_tiles(G), G.N, G.b != 2 && G.nonperiodic != 0, gen, nbj, aoff, ylo, ytile);
   return hipGetLastError();
 }
 
@@ -807,14 +865,14 @@ hipError_t launch_alg4(const Geometry &G, const DevSpec &D, int mode, const qmc_
   if (nitems > 0x7fffffffll) return hipErrorInvalidValue;
   a.nitems = (int32_t)nitems;
   a.nsteps = (int32_t)ceil_div(ps.sc, TK);
-  const bool add = G.b != 2;
+  const int idx = index_mode(G);
   const int gf = mode == kModeStoreY ? QMC_G_ID : f.g;
   // Items of four or more steps hide their own start and end: one item per
   // workgroup, scheduled by the hardware.  Shorter items (the lower pass of a
   // base b > 2): one resident wave of workgroups (a multiple of 8, one share
   // per XCD), each streaming a contiguous range of items.
   const bool stream = a.nsteps < 4;
-  const void *fn = prec == QMC_FP32 ? fn_p<QMC_FP32>(add, stream, mode, gf) : fn_p<QMC_SPLIT_BF16X3>(add, stream, mode, gf);
+  const void *fn = prec == QMC_FP32 ? fn_p<QMC_FP32>(idx, stream, mode, gf) : fn_p<QMC_SPLIT_BF16X3>(idx, stream, mode, gf);
   int64_t wgs = nitems;
   if (stream) wgs = round_up(std::min<int64_t>(nitems, std::max<int64_t>(resident_workgroups(fn, 256, 0), 8)), 8);
   const float *Ap = A + (int64_t)ps.j0 * lda;
@@ -865,8 +923,8 @@ hipError_t launch_alg4_adj(const Geometry &G, const DevSpec &D, int prec, const 
   const int64_t items = round_up(groups, 8) * a.jtiles;  // whole groups of 8 (one per XCD)
   if (items > 0x7fffffffll) return hipErrorInvalidValue;
   a.ngroups = (int32_t)groups;
-  const bool add = G.b != 2;
-  const void *fn = prec == QMC_FP32 ? adj_fn<QMC_FP32>(add, mi) : adj_fn<QMC_SPLIT_BF16X3>(add, mi);
+  const int idx = index_mode(G);
+  const void *fn = prec == QMC_FP32 ? adj_fn<QMC_FP32>(idx, mi) : adj_fn<QMC_SPLIT_BF16X3>(idx, mi);
   void *args[] = {&a, const_cast<DevSpec *>(&D), &tab, &Gm, &part};
   const hipError_t e = hipLaunchKernel(fn, dim3((unsigned)items), dim3(256), args, 0, st);
   return e != hipSuccess ? e : hipGetLastError();

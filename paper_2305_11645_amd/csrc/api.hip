@@ -426,8 +426,6 @@ qmc_status qmc_points_init(qmc_points *out, const qmc_point_spec *sp) {
         gen[(size_t)j * m + q] = (uint32_t)wd;
       }
     }
-    if (nonperiodic && b != 2)
-      return fail(QMC_EUNSUPPORTED, "a net in base %d must be periodic after reduction (Algorithm 4 is built for b = 2)", b);
   } else if (sp->kind == QMC_POLY_LATTICE && b != 2) {
     gen.resize(s);
     for (int j = 0; j < s; ++j) {
@@ -507,6 +505,11 @@ qmc_status qmc_points_init(qmc_points *out, const qmc_point_spec *sp) {
   if (gather_total >= kAlg4MaxValues)
     return fail(QMC_EUNSUPPORTED, "value tables of %lld floats reach %lld", (long long)gather_total,
                 (long long)kAlg4MaxValues);
+  // a net over F_b, b > 2, that is not periodic keeps one index word per point
+  // and coordinate
+  if (nonperiodic && b != 2 && ceil_div(Nb, 64) * 64 * s > kMaxIndexWords)
+    return fail(QMC_EUNSUPPORTED, "a net over F_%d that is not periodic needs N s = %lld index words (at most %lld)",
+                b, (long long)(Nb * s), (long long)kMaxIndexWords);
 
   qmc_points p = new qmc_points_s();
   p->device = device;
@@ -522,8 +525,14 @@ qmc_status qmc_points_init(qmc_points *out, const qmc_point_spec *sp) {
   plan_geometry(G, sp->w);
   // the cascade below is planned in base 2; a base b > 2 takes the gather path
   G.gather = nonperiodic || b != 2 ? 1 : 0;
-  if (nonperiodic) G.jlow = s;  // one pass over every coordinate
-  if (b != 2) plan_gather_split(G, sp->w, Nb);
+  if (nonperiodic) {  // one pass over every coordinate and point
+    G.N = Nb;
+    G.jlow = s;
+    G.split = -1;
+    G.nsub = 0;
+  } else if (b != 2) {
+    plan_gather_split(G, sp->w, Nb);
+  }
   G.gather_total = gather_total;
 
   auto cleanup = [&](qmc_status st) {
@@ -561,7 +570,10 @@ qmc_status qmc_points_init(qmc_points *out, const qmc_point_spec *sp) {
     return cleanup(hip_fail(e, "hipMemcpy"));
   if (G.gather) {  // gather path: table starts and index words, once
     std::vector<uint32_t> aoff(s);
-    if (nonperiodic) {
+    if (nonperiodic && b != 2) {
+      // one table of n_j values per coordinate, read by their output integer
+      for (int j = 0; j < s; ++j) aoff[j] = (uint32_t)soff[j];
+    } else if (nonperiodic) {
       // tables in order of decreasing n_j: every start is a multiple of its n_j
       std::vector<int> ord(s);
       for (int j = 0; j < s; ++j) ord[j] = j;

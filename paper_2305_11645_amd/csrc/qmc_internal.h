@@ -49,7 +49,7 @@ struct Level {
 struct Geometry {
   int32_t m, s, kind, rand, map, R;
   int32_t b;             // prime base: N = b^m, n_j = b^{m - min(w_j, m)}
-  int32_t nonperiodic;   // a reduced net that is not periodic: products by Algorithm 4
+  int32_t nonperiodic;   // a reduced net that is not periodic: products by Algorithm 4 (any prime b)
   int32_t gather;        // products by gathered value tiles on the matrix cores: nets that
                          // are not periodic (index by XOR) and every base b > 2 (index by add)
   int64_t gather_total;  // floats per randomisation in the value tables of the gather path
@@ -274,6 +274,7 @@ int64_t alg4_index_words(const Geometry &G);  // (64 + tiles) * s
 int alg4_col_tiles(int t);
 constexpr int64_t kAlg4MaxLda = int64_t(1) << 24;     // leading dimension of A
 constexpr int64_t kAlg4MaxValues = int64_t(1) << 30;  // value-table floats: below 2^30 (4-byte offsets < 2^32)
+constexpr int64_t kMaxIndexWords = int64_t(1) << 29;  // per-point index words (nets over F_b not periodic): 2 GiB
 // Adjoint of the gather path, dA = X^T G (Algorithm 4 transposed).
 // alg4_adj_chunks: point chunks of a pass over sc coordinates and npts points
 // (its partials hold nr x chunks x sc x t FP64 values).  launch_alg4_adj:

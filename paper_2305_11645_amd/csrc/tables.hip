@@ -56,9 +56,13 @@ __host__ __device__ __forceinline__ uint64_t ipow_u64(uint32_t b, int e) {
 // path in value_int)
 __device__ __noinline__ uint32_t value_int_b(const PointConsts &G, const uint32_t *__restrict__ gen, int j,
                                              uint32_t rho, int nb) {
+  if (G.by_output) return rho;  // already the integer of the output digits
   const uint32_t b = (uint32_t)G.b;
-  uint32_t rd[32], y[32];  // nb <= 24 (b^nb <= 2^24)
-  for (int i = 0; i < nb; ++i) {
+  // a net that is not periodic reads every digit of the point index (m <= 24)
+  const int nd = G.nonperiodic && G.kind == QMC_DIGITAL_NET ? G.m : nb;
+  uint32_t rd[32];
+  uint64_t y[32];  // sums of up to m products below b^2
+  for (int i = 0; i < nd; ++i) {
     rd[i] = rho % b;
     rho /= b;
     y[i] = 0;
@@ -71,23 +75,23 @@ __device__ __noinline__ uint32_t value_int_b(const PointConsts &G, const uint32_
     }
     uint32_t c = 0;
     for (int i = nb - 1; i >= 0; --i) {  // coefficient i of the product is digit i
-      uint32_t acc = 0;
-      for (int k = 0; k <= i; ++k) acc += rd[k] * gd[i - k];
-      c = c * b + acc % b;
+      uint64_t acc = 0;
+      for (int k = 0; k <= i; ++k) acc += (uint64_t)rd[k] * gd[i - k];
+      c = c * b + (uint32_t)(acc % b);
     }
     return c;
   }
   const uint32_t *col = gen + (size_t)j * G.m;
-  for (int q = 0; q < nb; ++q) {  // digits of rho past nb are zero
+  for (int q = 0; q < nd; ++q) {  // periodic: digits of rho past nb are zero
     if (!rd[q]) continue;
     uint32_t wd = col[q];
     for (int p = 0; p < nb; ++p) {
-      y[p] += (wd % b) * rd[q];
+      y[p] += (uint64_t)(wd % b) * rd[q];
       wd /= b;
     }
   }
   uint32_t c = 0;
-  for (int p = 0; p < nb; ++p) c = c * b + y[p] % b;
+  for (int p = 0; p < nb; ++p) c = c * b + (uint32_t)(y[p] % b);
   return c;
 }
 
@@ -427,7 +431,8 @@ hipError_t launch_point_matrix(const Geometry &G, const DevSpec &D, int r, float
 // flat index e over sum_j n_j is mapped to (j, rho) by a binary search over
 // soff.  Nets (digit order): rho is the digit word y, stored at aoff_j + y,
 // the value that of the output integer bitreverse(y).  Base b > 2: rho is the
-// residue, stored at aoff_j + rho and aoff_j + rho + n_j.
+// residue, stored at aoff_j + rho and aoff_j + rho + n_j; for a net over F_b
+// that is not periodic rho is the output integer c, stored once at aoff_j + c.
 template <bool INVNORM, int VB>
 __global__ __launch_bounds__(256) void outvals_kernel(PointConsts G, DevSpec D, int r0, int64_t stride,
                                                       float *__restrict__ out) {
@@ -445,6 +450,9 @@ __global__ __launch_bounds__(256) void outvals_kernel(PointConsts G, DevSpec D, 
     if constexpr (VB == 0) {
       const uint32_t c = nb == 0 ? 0u : __builtin_bitreverse32(y) >> (32 - nb);
       o[y] = (float)value_f64<INVNORM, 0>(G, D, r0 + rl, lo, c, nb);
+    } else if (G.nonperiodic) {
+      // a net over F_b that is not periodic: y is the output integer c itself
+      o[y] = (float)value_f64<INVNORM, VB>(G, D, r0 + rl, lo, y, nb);
     } else {
       const int64_t n = (lo + 1 < G.s ? D.soff[lo + 1] : total) - D.soff[lo];
       const float v = (float)value_f64<INVNORM, VB>(G, D, r0 + rl, lo, y, nb);

@@ -109,8 +109,8 @@ def lat3(**kw):
 
 
 BASE_CASES = [
-    ("b = 3 net not periodic", lambda wl: _spec(wl, kind=I.DIGITAL_NET,
-                                                gen=np.ones(10 * 5, dtype=np.uint64)), 2),
+    ("b = 3 net not periodic (Algorithm 4; stops at the device check)",
+     lambda wl: _spec(wl, kind=I.DIGITAL_NET, gen=np.ones(10 * 5, dtype=np.uint64)), 4),
     ("b = 3 polynomial lattice", lambda wl: _spec(wl, kind=I.POLY_LATTICE), 4),
     ("b = 3 polynomial without constant term", lambda wl: _spec(wl, kind=I.POLY_LATTICE,
                                                                 gen=np.r_[[3], wl.gen[1:]]), 1),
@@ -130,7 +130,7 @@ BASE_CASES = [
 def test_base_b_points_init_validation(name, make, code):
     """A prime base b > 2 (Sections 1.1, 1.3, 3): N = b^m up to 2^24, lattice
     generators units modulo b^{m-w_j}, polynomials with a nonzero constant
-    term, nets periodic after reduction, digital shifts below b^K (code 4: the
+    term, nets periodic after reduction or not, digital shifts below b^K (code 4: the
     spec is valid and the call reaches the device check, no GPU here)."""
     import torch
     if code == 4 and torch.cuda.is_available():

@@ -702,6 +702,113 @@ def test_base_b_gradient_kinds(kind):
     _check_grad(wl, q.Points.from_workload(wl))
 
 
+# ------------------------------------------------------------------ Algorithm 4 over F_b (b > 2)
+
+UPPER_B = [(3, 6), (5, 4), (7, 3)]   # N = 729, 625, 343
+
+
+def upper_b(b, m, rand=I.DIGITAL_SHIFT, mp=I.MAP_CENTER, s=45, t=100, R=2, seed=13, g=I.G_COS, h=I.H_ID, K=0.0,
+            c=1.0, A_scale=0.3):
+    R = R if rand != I.NO_SHIFT else 1
+    return I.make_custom(kind=I.DIGITAL_NET, m=m, s=s, t=t, w=I.w_logb(s, m + 1, b), rand=rand, R=R, map=mp, g=g,
+                         h=h, K=K, c=c, seed=seed, A_scale=A_scale, net="upper", b=b)
+
+
+def test_base_b_alg4_is_planned_for_upper_triangular_nets():
+    from oracle import oracle as O
+    torch_cuda()
+    for b, m in UPPER_B:
+        wl = upper_b(b, m)
+        assert not O.net_is_periodic(wl)
+        assert q.Points.from_workload(wl).split_level == -1
+
+
+@pytest.mark.parametrize("b,m", UPPER_B)
+@pytest.mark.parametrize("rand", RANDS)
+@pytest.mark.parametrize("mp", [I.MAP_ID, I.MAP_CENTER, I.MAP_INVNORM])
+def test_base_b_alg4_tables_bit_exact(b, m, rand, mp):
+    """Values indexed by the integer of the reduced output digits over F_b
+    (FP64) equal the oracle's bit for bit (the inverse-normal map to 1e-14)."""
+    from oracle import oracle as O
+    if mp == I.MAP_INVNORM and rand == I.NO_SHIFT:
+        pytest.skip("the inverse-normal map requires a shift")
+    torch_cuda()
+    wl = upper_b(b, m, rand, mp, s=20)
+    pts = q.Points.from_workload(wl)
+    for r in range(wl.R):
+        for j in range(wl.s):
+            got = q.point_values(pts, r, j).cpu().numpy()
+            ref = O.output_values(wl, r, j)
+            if mp == I.MAP_INVNORM:
+                np.testing.assert_allclose(got, ref, rtol=1e-14, atol=0)
+            else:
+                np.testing.assert_array_equal(got, ref)
+
+
+@pytest.mark.parametrize("b,m", UPPER_B)
+def test_base_b_alg4_point_matrix_matches_unreduced(b, m):
+    from oracle import oracle as O
+    torch_cuda()
+    wl = upper_b(b, m, s=30)
+    pts = q.Points.from_workload(wl)
+    for r in range(wl.R):
+        X = q.point_matrix(pts, r).cpu().numpy()
+        np.testing.assert_array_equal(X, O.point_matrix_unreduced(wl, r).astype(np.float32))
+
+
+@pytest.mark.parametrize("b,m", UPPER_B)
+@pytest.mark.parametrize("prec", [I.FP32, I.SPLIT_BF16X3])
+def test_base_b_alg4_matvec_elementwise(b, m, prec):
+    """Y = X A over every element within the FP32 (or split-BF16) bound: more
+    than one 64-point tile (N not a multiple of 64), coordinates past one
+    32-coordinate step, two column tiles with a ragged tail (t = 300)."""
+    torch = torch_cuda()
+    wl = upper_b(b, m, t=300)
+    pts = q.Points.from_workload(wl)
+    A = to_dev(wl.A, torch)
+    for r in range(wl.R):
+        Y = q.reduced_matvec(pts, A, r=r, prec=prec).cpu().numpy()
+        _check_Y(wl, Y, r, prec)
+
+
+@pytest.mark.parametrize("b,m", UPPER_B)
+@pytest.mark.parametrize("g,h,c,mp", [(I.G_COS, I.H_ID, 1.0, I.MAP_CENTER), (I.G_EXP, I.H_CALL, 0.2, I.MAP_INVNORM)])
+def test_base_b_alg4_estimate_and_gradient(b, m, g, h, c, mp):
+    """Estimates within 1e-6 of the oracle; dQ/dA element by element within
+    its bound and within 1e-6 (Frobenius), Algorithm 4 transposed over F_b."""
+    from oracle import oracle as O
+    torch = torch_cuda()
+    K = 1.0 if h == I.H_CALL else 0.0
+    wl = upper_b(b, m, I.DIGITAL_SHIFT, mp, g=g, h=h, c=c, K=K)
+    pts = q.Points.from_workload(wl)
+    Q = q.estimate(pts, to_dev(wl.A, torch), q.Integrand_.of(wl)).cpu().numpy()
+    Qo, _ = O.estimate(wl)
+    assert np.all(np.abs(Q - Qo) <= Q_TOL * np.maximum(np.abs(Qo), 1e-3)), (Q, Qo)
+    _check_grad(wl, pts)
+
+
+def test_base_b_alg4_static_scratch_and_autograd():
+    """The allocation-free estimate and the autograd hook on a base-5 net that
+    is not periodic."""
+    import ctypes as ct
+    torch = torch_cuda()
+    wl = upper_b(5, 4, R=2)
+    pts = q.Points.from_workload(wl)
+    A = to_dev(wl.A, torch)
+    f = q.Integrand_.of(wl)
+    Qs = torch.empty(2, dtype=torch.float64, device="cuda")
+    L = q.load()
+    st = ct.c_void_p(torch.cuda.current_stream().cuda_stream)
+    q._lib.check(L.qmc_estimate_static(pts.handle, ct.c_void_p(A.data_ptr()), wl.t, wl.t, ct.byref(f.c_struct()), 0,
+                                       ct.c_void_p(Qs.data_ptr()), st))
+    assert torch.equal(Qs, q.estimate(pts, A, f))
+    Ag = A.clone().requires_grad_(True)
+    Qa = q.QMCEstimate.apply(Ag, pts, f, I.FP32)
+    Qa.sum().backward()
+    _, dA = q.estimate_grad(pts, A, f)
+    assert torch.allclose(Ag.grad, dA.double().sum(0).float(), rtol=1e-6, atol=1e-12)
+
+
 # ------------------------------------------------------------------ full-size workloads
 
 def _expected():
