@@ -175,12 +175,13 @@ enum Op { kOpMatvec = 0, kOpEstimate = 1, kOpGrad = 2 };
 
 struct Work {
   float *tables, *U, *ppart, *S, *dlow, *dup, *hd, *root;
+  void *bsplit;  // split BF16: the (hi, lo) operands of the upper-level products
   float *Gm;  // gather path, gradient: the sensitivities G, [nr][N][t]
   double *partial, *ppartial;
   double *glow, *gup;  // gather path, gradient: FP64 chunk partials of dA
 };
 
-size_t carve(const qmc::Geometry &G, int op, int t, const qmc_integrand *f, int nr, char *base,
+size_t carve(const qmc::Geometry &G, int op, int t, const qmc_integrand *f, int nr, int prec, char *base,
              Work &wk) {
   using namespace qmc;
   Carve c{base};
@@ -211,6 +212,7 @@ size_t carve(const qmc::Geometry &G, int op, int t, const qmc_integrand *f, int 
   }
   wk.tables = c.take<float>((size_t)nr * G.table_total + kTablePad);
   wk.U = c.take<float>((size_t)nr * G.urows * ldu);
+  if (prec == QMC_SPLIT_BF16X3 && G.nup > 0) wk.bsplit = c.take<char>((size_t)levels_split_bytes(G, nr, t));
   if (op == kOpMatvec) return c.used;
   const bool sep = f->h == QMC_H_ID;
   wk.partial = c.take<double>((size_t)nr * std::max(lp.gx * lp.gy, lg.gx * lg.gy));
@@ -672,7 +674,7 @@ qmc_status qmc_workspace_size(qmc_points p, int32_t op, int32_t t, const qmc_int
   }
   DeviceGuard dg(p->device);  // the leaf plan queries the device's occupancy
   Work wk;
-  *bytes = carve(p->G, op, t, f, op == kOpMatvec ? 1 : p->G.R, nullptr, wk);
+  *bytes = carve(p->G, op, t, f, op == kOpMatvec ? 1 : p->G.R, prec, nullptr, wk);
   return QMC_OK;
 }
 
@@ -780,11 +782,11 @@ qmc_status qmc_reduced_matvec(qmc_points p, int32_t r, const float *A, int32_t t
   hipStream_t st = (hipStream_t)stream;
   const qmc_integrand fid{QMC_G_ID, 0.0, QMC_H_ID, 0.0};
   Work wk;
-  const size_t need = carve(p->G, kOpMatvec, t, &fid, 1, nullptr, wk);
+  const size_t need = carve(p->G, kOpMatvec, t, &fid, 1, prec, nullptr, wk);
   CallWorkspace own;
   char *base = nullptr;
   if (qmc_status s2 = get_workspace(p, need, workspace, workspace_bytes, st, own, base)) return s2;
-  carve(p->G, kOpMatvec, t, &fid, 1, base, wk);
+  carve(p->G, kOpMatvec, t, &fid, 1, prec, base, wk);
   const int64_t ldu = round_up(t, kTileT);
   const Geometry &G = p->G;
   if (G.gather) {  // gathered value tiles
@@ -797,7 +799,7 @@ qmc_status qmc_reduced_matvec(qmc_points p, int32_t r, const float *A, int32_t t
     return QMC_OK;
   }
   QMC_HIP(launch_tables(G, p->D, r, 1, wk.tables, nullptr, 0, st), "tables launch");
-  QMC_HIP(launch_levels(G, prec, wk.tables, 1, A, t, lda, wk.U, ldu, 1.0f, st), "levels launch");
+  QMC_HIP(launch_levels(G, prec, wk.tables, 1, A, t, lda, wk.U, ldu, 1.0f, wk.bsplit, st), "levels launch");
   LeafOut o{};
   o.Y = Y;
   o.ldy = ldy;
@@ -821,11 +823,11 @@ static qmc_status estimate_impl(qmc_points p, const float *A, int32_t t, int64_t
   const int nr = G.R;
   const int op = grad ? kOpGrad : kOpEstimate;
   Work wk;
-  const size_t need = carve(G, op, t, f, nr, nullptr, wk);
+  const size_t need = carve(G, op, t, f, nr, prec, nullptr, wk);
   CallWorkspace own;
   char *base = nullptr;
   if (qmc_status s2 = get_workspace(p, need, workspace, workspace_bytes, st, own, base)) return s2;
-  carve(G, op, t, f, nr, base, wk);
+  carve(G, op, t, f, nr, prec, base, wk);
   const int64_t ldu = round_up(t, kTileT);
   const int tct = (int)ceil_div(t, kTileT);
   const LeafPlan lp = leaf_plan(G, t, nr, kModeSum, f->g);
@@ -860,7 +862,7 @@ static qmc_status estimate_impl(qmc_points p, const float *A, int32_t t, int64_t
 
   QMC_HIP(launch_tables(G, p->D, 0, nr, wk.tables, nullptr, 0, st), "tables launch");
   const int leaf_mode = !sep ? kModePoint : (grad ? kModeGrad : kModeSum);
-  QMC_HIP(launch_levels(G, prec, wk.tables, nr, A, t, lda, wk.U, ldu, g_scale(*f, leaf_mode), st),
+  QMC_HIP(launch_levels(G, prec, wk.tables, nr, A, t, lda, wk.U, ldu, g_scale(*f, leaf_mode), wk.bsplit, st),
           "levels launch");
   LeafOut o{};
   if (sep) {
@@ -912,7 +914,7 @@ qmc_status qmc_estimate_static(qmc_points p, const float *A, int32_t t, int64_t 
   if (!Q) return fail(QMC_EINVAL, "Q is null");
   DeviceGuard dg(p->device);
   Work wk;
-  const size_t need = carve(p->G, kOpEstimate, t, f, p->G.R, nullptr, wk);
+  const size_t need = carve(p->G, kOpEstimate, t, f, p->G.R, prec, nullptr, wk);
   if (need > kStaticScratchBytes)
     return fail(QMC_ENOMEM, "the estimate needs %zu bytes of workspace; the static scratch holds %zu",
                 need, (size_t)kStaticScratchBytes);

@@ -20,6 +20,8 @@
 //                 D: acc[v] = D[8(v/4) + 4(l/32) + v%4][l%32].
 //   32x32x16 bf16: A: lane l holds A[l%32][8(l/32) + 0..7]; B: B[8(l/32)+0..7][l%32];
 //                 D as above.
+#include <algorithm>
+
 #include "qmc_internal.h"
 
 namespace qmc {
@@ -193,6 +195,233 @@ __global__ __launch_bounds__(256) void levels_gemm(GemmArgs g, const float *__re
   }
 }
 
+// ------------------------------------------------------------------ split BF16, operands split once
+// The forward level products in split BF16 with both operands split into
+// (hi, lo) once per call instead of inside the product loop:
+//   split_kernel   the upper-level tables X~_I (per randomisation, rows padded
+//                  to a multiple of 8 values) and the rows of A of the upper
+//                  levels, transposed so that K is contiguous for both operands
+//                  (A^T[col][koff_I + k], koff_I a multiple of 8);
+//   gemm_bf16x3    128 x 128 output tiles, four waves of 64 x 64 (four 32 x 32
+//                  MFMA blocks each), K-steps of 16 loaded as 16-byte chunks,
+//                  two LDS buffers; per block and step lo*hi, hi*lo, hi*hi on
+//                  v_mfma_f32_32x32x16_bf16 into one FP32 accumulator.
+typedef __bf16 bf16x8v __attribute__((ext_vector_type(8)));
+
+constexpr int SBM = 128, SBN = 128, SBK = 16;
+constexpr int SRS = SBK + 8;  // LDS row stride in bf16: 48 bytes, so eight lanes' 16-byte reads hit distinct banks
+
+struct SplitLayout {
+  int64_t up_pad;                  // bf16 of one randomisation's split upper tables (hi or lo)
+  int64_t kpad;                    // padded upper coordinates: row stride of the split A^T
+  int64_t tab_off[kMaxLevels];     // per upper level u: offset of its split table (bf16)
+  int32_t koff[kMaxLevels];        // per upper level u: first K index in the split A^T
+  int32_t taup[kMaxLevels];        // per upper level u: tau_I rounded up to 8
+};
+
+static SplitLayout split_layout(const Geometry &G) {
+  SplitLayout L{};
+  int64_t off = 0;
+  int32_t k = 0;
+  for (int u = 0; u < G.nup; ++u) {
+    const Level &lv = G.lev[G.up[u]];
+    L.taup[u] = (int32_t)round_up(lv.tau, 8);
+    L.tab_off[u] = off;
+    L.koff[u] = k;
+    off += (int64_t(1) << lv.nb) * L.taup[u];
+    k += L.taup[u];
+  }
+  L.up_pad = off;
+  L.kpad = k;
+  return L;
+}
+
+int64_t levels_split_bytes(const Geometry &G, int nr, int t) {
+  const SplitLayout L = split_layout(G);
+  return 2 * 2 * ((int64_t)nr * L.up_pad + L.kpad * (int64_t)t);  // hi and lo, 2 bytes each
+}
+
+struct SplitArgs {
+  Geometry G;
+  SplitLayout L;
+  int32_t nr, t;
+  int64_t lda;
+};
+
+// Elements: [nr][up_pad] table values, then [t][kpad] of A^T.  Padding reads 0.
+__global__ __launch_bounds__(256) void split_kernel(SplitArgs a, const float *__restrict__ tables,
+                                                    const float *__restrict__ A, __bf16 *__restrict__ hi,
+                                                    __bf16 *__restrict__ lo) {
+  const Geometry &G = a.G;
+  const int64_t ntab = (int64_t)a.nr * a.L.up_pad, total = ntab + (int64_t)a.t * a.L.kpad;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+    float x = 0.f;
+    if (e < ntab) {
+      const int64_t r = e / a.L.up_pad, o = e - r * a.L.up_pad;
+      int u = 0;
+      while (u + 1 < G.nup && a.L.tab_off[u + 1] <= o) ++u;
+      const Level &lv = G.lev[G.up[u]];
+      const int64_t q = o - a.L.tab_off[u], row = q / a.L.taup[u], k = q - row * a.L.taup[u];
+      if (k < lv.tau) x = tables[r * G.table_total + G.lower_total + lv.off + row * lv.tau + k];
+    } else {
+      const int64_t q = e - ntab, col = q / a.L.kpad, kk = q - col * a.L.kpad;
+      int u = 0;
+      while (u + 1 < G.nup && a.L.koff[u + 1] <= kk) ++u;
+      const Level &lv = G.lev[G.up[u]];
+      const int64_t k = kk - a.L.koff[u];
+      if (k < lv.tau) x = A[(int64_t)(lv.j0 + k) * a.lda + col];
+    }
+    const __bf16 h = (__bf16)x;
+    hi[e] = h;
+    lo[e] = (__bf16)(x - (float)h);
+  }
+}
+
+struct SplitGemmArgs {
+  int32_t tile0[kMaxGemmProbs];
+  int32_t nprob;
+  float oscale;
+  int64_t a_rs, c_rs, ldc, kpad;
+  struct {
+    int32_t M, K, tiles_n;
+    int64_t a_off, b_off, c_off;
+  } p[kMaxLevels];
+};
+
+__global__ __launch_bounds__(256) void gemm_bf16x3(SplitGemmArgs g, int N, const __bf16 *__restrict__ Ahi,
+                                                   const __bf16 *__restrict__ Alo,
+                                                   const __bf16 *__restrict__ Bhi,
+                                                   const __bf16 *__restrict__ Blo, float *__restrict__ Cbase) {
+  __shared__ __attribute__((aligned(16))) __bf16 As[2][2][SBM * SRS];  // [buffer][hi, lo][row][k]
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[2][2][SBN * SRS];  // [buffer][hi, lo][col][k]
+  const int r = blockIdx.y;
+  int tile = blockIdx.x;
+  int pi = 0;
+#pragma unroll
+  for (int q = 1; q < kMaxGemmProbs; ++q)
+    if (tile >= g.tile0[q]) pi = q;
+  const auto &P = g.p[pi];
+  tile -= g.tile0[pi];
+  const int tn = tile % P.tiles_n, tm = tile / P.tiles_n;
+  const int i0 = tm * SBM, j0 = tn * SBN;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wr = (w >> 1) * 64, wc = (w & 1) * 64;
+  // loader: row (A) or column (B) ld = tid / 2, 8 K-values at kh = 8 (tid % 2)
+  const int ld = tid >> 1, kh = 8 * (tid & 1);
+  const int64_t aoff = r * g.a_rs + P.a_off;
+  const bool arow_ok = i0 + ld < P.M, bcol_ok = j0 + ld < N;
+  const __bf16 *ah_p = Ahi + aoff + (int64_t)(arow_ok ? i0 + ld : 0) * P.K + kh;
+  const __bf16 *al_p = Alo + aoff + (int64_t)(arow_ok ? i0 + ld : 0) * P.K + kh;
+  const __bf16 *bh_p = Bhi + P.b_off + (int64_t)(bcol_ok ? j0 + ld : 0) * g.kpad + kh;
+  const __bf16 *bl_p = Blo + P.b_off + (int64_t)(bcol_ok ? j0 + ld : 0) * g.kpad + kh;
+  bf16x8v ra[2], rb[2];
+  const bf16x8v zero = {};
+  auto load = [&](int k0) {
+    const bool kok = k0 + kh < P.K;  // K is a multiple of 8: a chunk is whole or absent
+    ra[0] = arow_ok && kok ? *reinterpret_cast<const bf16x8v *>(ah_p + k0) : zero;
+    ra[1] = arow_ok && kok ? *reinterpret_cast<const bf16x8v *>(al_p + k0) : zero;
+    rb[0] = bcol_ok && kok ? *reinterpret_cast<const bf16x8v *>(bh_p + k0) : zero;
+    rb[1] = bcol_ok && kok ? *reinterpret_cast<const bf16x8v *>(bl_p + k0) : zero;
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      *reinterpret_cast<bf16x8v *>(&As[buf][h][ld * SRS + kh]) = ra[h];
+      *reinterpret_cast<bf16x8v *>(&Bs[buf][h][ld * SRS + kh]) = rb[h];
+    }
+  };
+  f32x16 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x16{0};
+  load(0);
+  store(0);
+  __syncthreads();
+  int cur = 0;
+  const int ko = 8 * (lane >> 5);  // this lane's K-values of a step: ko .. ko + 7
+  for (int k0 = 0; k0 < P.K; k0 += SBK) {
+    const bool more = k0 + SBK < P.K;
+    if (more) load(k0 + SBK);
+    bf16x8v xa[2][2], xb[2][2];  // [block][hi, lo]
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        xa[i][h] = *reinterpret_cast<const bf16x8v *>(&As[cur][h][(wr + 32 * i + (lane & 31)) * SRS + ko]);
+        xb[i][h] = *reinterpret_cast<const bf16x8v *>(&Bs[cur][h][(wc + 32 * i + (lane & 31)) * SRS + ko]);
+      }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xa[i][1], xb[j][0], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xa[i][0], xb[j][1], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xa[i][0], xb[j][0], acc[i][j], 0, 0, 0);
+      }
+    if (more) store(cur ^ 1);
+    __syncthreads();
+    cur ^= 1;
+  }
+  float *Cb = Cbase + r * g.c_rs + P.c_off;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int col = j0 + wc + 32 * j + (lane & 31);
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int row = i0 + wr + 32 * i + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        if (row < P.M && col < N)
+          __builtin_nontemporal_store(g.oscale * acc[i][j][v], &Cb[(int64_t)row * g.ldc + col]);
+      }
+    }
+}
+
+static hipError_t launch_levels_split(const Geometry &G, const float *tables, int nr, const float *A, int t,
+                                      int64_t lda, float *U, int64_t ldu, float oscale, void *bsplit,
+                                      hipStream_t st) {
+  const SplitLayout L = split_layout(G);
+  __bf16 *hi = static_cast<__bf16 *>(bsplit);
+  const int64_t half = (int64_t)nr * L.up_pad + L.kpad * (int64_t)t;  // elements per hi / lo array
+  __bf16 *lo = hi + half;
+  SplitArgs sa;
+  sa.G = G;
+  sa.L = L;
+  sa.nr = nr;
+  sa.t = t;
+  sa.lda = lda;
+  const int64_t blocks = std::min<int64_t>(ceil_div(half, 256), 16384);
+  hipLaunchKernelGGL(split_kernel, dim3((unsigned)blocks), dim3(256), 0, st, sa, tables, A, hi, lo);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  SplitGemmArgs g{};
+  g.nprob = G.nup;
+  g.oscale = oscale;
+  g.a_rs = L.up_pad;
+  g.c_rs = G.urows * ldu;
+  g.ldc = ldu;
+  g.kpad = L.kpad;
+  int tiles = 0;
+  for (int u = 0; u < G.nup; ++u) {
+    const Level &lv = G.lev[G.up[u]];
+    auto &P = g.p[u];
+    P.M = 1 << lv.nb;
+    P.K = L.taup[u];
+    P.tiles_n = (int)ceil_div(t, SBN);
+    P.a_off = L.tab_off[u];
+    P.b_off = (int64_t)nr * L.up_pad + L.koff[u];
+    P.c_off = lv.uoff * ldu;
+    g.tile0[u] = tiles;
+    tiles += (int)ceil_div(P.M, SBM) * P.tiles_n;
+  }
+  for (int q = G.nup; q < kMaxGemmProbs; ++q) g.tile0[q] = 0x7fffffff;
+  if (tiles == 0 || nr == 0) return hipSuccess;
+  // B (the split A^T) lives after the tables in both arrays: its offset is in b_off
+  hipLaunchKernelGGL(gemm_bf16x3, dim3(tiles, nr), dim3(256), 0, st, g, t, hi, lo, hi, lo, U);
+  return hipGetLastError();
+}
+
 template <bool TA>
 static hipError_t run_gemm(const GemmArgs &a, int prec, int nr, const float *A, const float *B,
                            float *C, hipStream_t st) {
@@ -206,8 +435,10 @@ static hipError_t run_gemm(const GemmArgs &a, int prec, int nr, const float *A, 
 }
 
 hipError_t launch_levels(const Geometry &G, int prec, const float *tables, int nr, const float *A,
-                         int t, int64_t lda, float *U, int64_t ldu, float oscale, hipStream_t st) {
+                         int t, int64_t lda, float *U, int64_t ldu, float oscale, void *bsplit, hipStream_t st) {
   LaunchTimer tm("levels", st);
+  if (prec == QMC_SPLIT_BF16X3 && bsplit && G.nup > 0)
+    return launch_levels_split(G, tables, nr, A, t, lda, U, ldu, oscale, bsplit, st);
   GemmArgs a = {};
   a.oscale = oscale;
   a.a_rs = G.table_total;
