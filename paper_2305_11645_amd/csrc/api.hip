@@ -175,7 +175,7 @@ enum Op { kOpMatvec = 0, kOpEstimate = 1, kOpGrad = 2 };
 
 struct Work {
   float *tables, *U, *ppart, *S, *dlow, *dup, *hd, *root;
-  void *bsplit;  // split BF16: the (hi, lo) operands of the upper-level products
+  void *bsplit;  // the packed operands of the upper-level products
   float *Gm;  // gather path, gradient: the sensitivities G, [nr][N][t]
   double *partial, *ppartial;
   double *glow, *gup;  // gather path, gradient: FP64 chunk partials of dA
@@ -212,7 +212,7 @@ size_t carve(const qmc::Geometry &G, int op, int t, const qmc_integrand *f, int 
   }
   wk.tables = c.take<float>((size_t)nr * G.table_total + kTablePad);
   wk.U = c.take<float>((size_t)nr * G.urows * ldu);
-  if (prec == QMC_SPLIT_BF16X3 && G.nup > 0) wk.bsplit = c.take<char>((size_t)levels_split_bytes(G, nr, t));
+  if (G.nup > 0) wk.bsplit = c.take<char>((size_t)levels_split_bytes(G, nr, t));
   if (op == kOpMatvec) return c.used;
   const bool sep = f->h == QMC_H_ID;
   wk.partial = c.take<double>((size_t)nr * std::max(lp.gx * lp.gy, lg.gx * lg.gy));

@@ -4,22 +4,28 @@
 //     U_I = X~_I A_I,      X~_I: n_I x tau_I point table, A_I: rows G_I of A.
 // Adjoint (transpose of the same step):
 //     dA_I = X~_I^T S_I,   S_I: n_I x t sums of dQ/dy over the residue classes.
-// All levels and all randomisations go in one launch; every workgroup owns
-// one 64 x 64 output tile of one (level, shift, K-chunk).  The adjoint
-// contracts over n_I rows, so it is split into K-chunks of at most 1024 whose
-// FP32 partials are combined later in FP64.
+// All levels and all randomisations go in one launch.  The forward operands
+// are packed once per call into K-step slabs (the section "forward, packed
+// operands" below), and each workgroup owns a 128 x 256 output tile.  In the
+// adjoint every workgroup owns one 64 x 64 output tile of one (level, shift,
+// K-chunk); it contracts over n_I rows, so it is split into K-chunks of at
+// most 1024 whose FP32 partials are combined later in FP64.
 //
 // Precision:
-//   FP32        v_mfma_f32_32x32x2_f32, FP32 accumulation.
+//   FP32        forward v_mfma_f32_16x16x4_f32, adjoint v_mfma_f32_32x32x2_f32,
+//               FP32 accumulation.
 //   SPLIT_BF16  each FP32 operand x = hi + lo with hi = bf16(x),
-//               lo = bf16(x - hi); hi*hi on one accumulator, hi*lo + lo*hi on
-//               a second, v_mfma_f32_32x32x16_bf16, summed at the end.
+//               lo = bf16(x - hi); lo*hi + hi*lo + hi*hi (forward, one
+//               accumulator) or hi*hi on one and hi*lo + lo*hi on a second
+//               (adjoint), v_mfma_f32_32x32x16_bf16.
 //
-// MFMA operand layouts (wave64, one 32 x 32 block):
+// MFMA operand layouts (wave64):
 //   32x32x2 f32:  A: lane l holds A[l%32][l/32]; B: B[l/32][l%32];
 //                 D: acc[v] = D[8(v/4) + 4(l/32) + v%4][l%32].
+//   16x16x4 f32:  A: lane l holds A[l%16][l/16]; B: B[l/16][l%16];
+//                 D: acc[v] = D[4(l/16) + v][l%16].
 //   32x32x16 bf16: A: lane l holds A[l%32][8(l/32) + 0..7]; B: B[8(l/32)+0..7][l%32];
-//                 D as above.
+//                 D as for 32x32x2.
 #include <algorithm>
 
 #include "qmc_internal.h"
@@ -195,50 +201,69 @@ __global__ __launch_bounds__(256) void levels_gemm(GemmArgs g, const float *__re
   }
 }
 
-// ------------------------------------------------------------------ split BF16, operands split once
-// The forward level products in split BF16 with both operands split into
-// (hi, lo) once per call instead of inside the product loop:
-//   split_kernel   the upper-level tables X~_I (per randomisation, rows padded
-//                  to a multiple of 8 values) and the rows of A of the upper
-//                  levels, transposed so that K is contiguous for both operands
-//                  (A^T[col][koff_I + k], koff_I a multiple of 8);
-//   gemm_bf16x3    128 x 128 output tiles, four waves of 64 x 64 (four 32 x 32
-//                  MFMA blocks each), K-steps of 16 loaded as 16-byte chunks,
-//                  two LDS buffers; per block and step lo*hi, hi*lo, hi*hi on
+// ------------------------------------------------------------------ forward, packed operands
+// The forward level products with both operands packed once per call into
+// K-step slabs (FP32), or split into (hi, lo) and packed (split BF16):
+//   pack_kernel    the upper-level tables X~_I (per randomisation) and the rows
+//                  of A of the upper levels, zero-padded to whole tiles and
+//                  K-steps of 16;
+//   gemm_f32p      FP32: v_mfma_f32_16x16x4_f32;
+//   gemm_bf16x3    split BF16: per block pair and K-step lo*hi, hi*lo, hi*hi on
 //                  v_mfma_f32_32x32x16_bf16 into one FP32 accumulator.
+// Both: 128 x 256 output tiles, four waves of 64 x 128, two LDS buffers, and
+// an epilogue that stages each wave's rows through LDS so that every store is
+// a 512-byte run of one output row.
+// Slab layout: the operand rows of one tile (128 table rows, or 256 columns of
+// A) for one K-step of 16 are one contiguous slab [k / RUN][row][k % RUN], RUN
+// = 4 values (FP32) or 8 (BF16) = 16 bytes.  A slab is copied to LDS unchanged
+// with 16-byte loads and stores in lane order, and a wave's fragment reads
+// (lane groups on consecutive rows at one k / RUN) are contiguous runs: no bank
+// conflicts and no predicates in the product loop.  In FP32 lane group g of a
+// 16 x 16 x 4 block holds k = 4 g .. 4 g + 3 in one 16-byte read, and the
+// block's four MFMAs of a K-step contract k = c, 4 + c, 8 + c, 12 + c (c =
+// 0..3): every k once, in another order.
 typedef __bf16 bf16x8v __attribute__((ext_vector_type(8)));
+typedef float f32x4v __attribute__((ext_vector_type(4)));
 
-constexpr int SBM = 128, SBN = 128, SBK = 16;
-constexpr int SRS = SBK + 8;  // LDS row stride in bf16: 48 bytes, so eight lanes' 16-byte reads hit distinct banks
+constexpr int SBM = 128, SBN = 256, SBK = 16;
+constexpr int SLAB_A = SBM * SBK, SLAB_B = SBN * SBK;  // values per slab
 
 struct SplitLayout {
-  int64_t up_pad;                  // bf16 of one randomisation's split upper tables (hi or lo)
-  int64_t kpad;                    // padded upper coordinates: row stride of the split A^T
-  int64_t tab_off[kMaxLevels];     // per upper level u: offset of its split table (bf16)
-  int32_t koff[kMaxLevels];        // per upper level u: first K index in the split A^T
-  int32_t taup[kMaxLevels];        // per upper level u: tau_I rounded up to 8
+  int64_t up_pad;                  // values of one randomisation's packed upper tables
+  int64_t kpad;                    // padded upper coordinates (K-steps of 16) of the packed A
+  int32_t ntn;                     // column tiles of 256
+  int64_t tab_off[kMaxLevels];     // per upper level u: offset of its packed table
+  int32_t koff[kMaxLevels];        // per upper level u: first K index in the packed A
+  int32_t taup[kMaxLevels];        // per upper level u: tau_I rounded up to 16
+  int32_t tiles_m[kMaxLevels];     // per upper level u: row tiles of 128
 };
 
-static SplitLayout split_layout(const Geometry &G) {
+static SplitLayout split_layout(const Geometry &G, int t) {
   SplitLayout L{};
   int64_t off = 0;
   int32_t k = 0;
   for (int u = 0; u < G.nup; ++u) {
     const Level &lv = G.lev[G.up[u]];
-    L.taup[u] = (int32_t)round_up(lv.tau, 8);
+    L.taup[u] = (int32_t)round_up(lv.tau, SBK);
+    L.tiles_m[u] = (int32_t)ceil_div(int64_t(1) << lv.nb, SBM);
     L.tab_off[u] = off;
     L.koff[u] = k;
-    off += (int64_t(1) << lv.nb) * L.taup[u];
+    off += (int64_t)L.tiles_m[u] * SBM * L.taup[u];
     k += L.taup[u];
   }
   L.up_pad = off;
   L.kpad = k;
+  L.ntn = (int32_t)ceil_div(t, SBN);
   return L;
 }
 
+// values of the packed tables of nr randomisations plus the packed A
+static int64_t packed_values(const SplitLayout &L, int nr) {
+  return (int64_t)nr * L.up_pad + (int64_t)L.ntn * SBN * L.kpad;
+}
+
 int64_t levels_split_bytes(const Geometry &G, int nr, int t) {
-  const SplitLayout L = split_layout(G);
-  return 2 * 2 * ((int64_t)nr * L.up_pad + L.kpad * (int64_t)t);  // hi and lo, 2 bytes each
+  return 4 * packed_values(split_layout(G, t), nr);  // FP32, or bf16 hi and lo
 }
 
 struct SplitArgs {
@@ -246,34 +271,68 @@ struct SplitArgs {
   SplitLayout L;
   int32_t nr, t;
   int64_t lda;
+  int64_t half;  // split BF16: values per hi / lo array
 };
 
-// Elements: [nr][up_pad] table values, then [t][kpad] of A^T.  Padding reads 0.
-__global__ __launch_bounds__(256) void split_kernel(SplitArgs a, const float *__restrict__ tables,
-                                                    const float *__restrict__ A, __bf16 *__restrict__ hi,
-                                                    __bf16 *__restrict__ lo) {
+// Arrays: [nr][up_pad] of the tables, then [ntn * 256 * kpad] of A, both in
+// slab order; padding (rows past n_I, columns past t, k past tau_I) is 0.
+// One thread writes one run of RUN k-values (16 bytes; in split BF16 16 bytes
+// of hi and of lo).  With tab, blockIdx.y = r packs randomisation r's tables;
+// else the A (grid y = 1).
+template <bool F32>
+__global__ __launch_bounds__(256) void pack_kernel(SplitArgs a, bool tab, const float *__restrict__ tables,
+                                                   const float *__restrict__ A, void *__restrict__ out) {
+  constexpr int RUN = F32 ? 4 : 8;
   const Geometry &G = a.G;
-  const int64_t ntab = (int64_t)a.nr * a.L.up_pad, total = ntab + (int64_t)a.t * a.L.kpad;
-  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
-    float x = 0.f;
-    if (e < ntab) {
-      const int64_t r = e / a.L.up_pad, o = e - r * a.L.up_pad;
+  const int r = blockIdx.y;
+  const int64_t runs = (tab ? a.L.up_pad : (int64_t)a.L.ntn * SBN * a.L.kpad) / RUN;
+  const int64_t base = tab ? (int64_t)r * a.L.up_pad : (int64_t)a.nr * a.L.up_pad;  // the A follows the tables
+  for (int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x; c < runs; c += (int64_t)gridDim.x * 256) {
+    const int64_t q0 = c * RUN;
+    float x[RUN];
+    if (tab) {
       int u = 0;
-      while (u + 1 < G.nup && a.L.tab_off[u + 1] <= o) ++u;
+      while (u + 1 < G.nup && a.L.tab_off[u + 1] <= q0) ++u;
       const Level &lv = G.lev[G.up[u]];
-      const int64_t q = o - a.L.tab_off[u], row = q / a.L.taup[u], k = q - row * a.L.taup[u];
-      if (k < lv.tau) x = tables[r * G.table_total + G.lower_total + lv.off + row * lv.tau + k];
+      const int64_t q = q0 - a.L.tab_off[u];
+      const uint32_t slab = (uint32_t)(q / SLAB_A), in = (uint32_t)(q % SLAB_A);
+      const uint32_t ksteps = (uint32_t)a.L.taup[u] / SBK;
+      const int64_t row = (int64_t)(slab / ksteps) * SBM + (in % (SBM * RUN)) / RUN;
+      const int k0 = (int)(slab % ksteps) * SBK + (int)(in / (SBM * RUN)) * RUN;
+      const bool rok = row < (int64_t(1) << lv.nb);
+      const float *src = tables + r * G.table_total + G.lower_total + lv.off + (rok ? row : 0) * lv.tau;
+#pragma unroll
+      for (int i = 0; i < RUN; ++i) x[i] = rok && k0 + i < lv.tau ? src[k0 + i] : 0.f;
     } else {
-      const int64_t q = e - ntab, col = q / a.L.kpad, kk = q - col * a.L.kpad;
+      const uint32_t ksteps = (uint32_t)(a.L.kpad / SBK);
+      const uint32_t slab = (uint32_t)(q0 / SLAB_B), in = (uint32_t)(q0 % SLAB_B);
+      const int64_t col = (int64_t)(slab / ksteps) * SBN + (in % (SBN * RUN)) / RUN;
+      const int kk0 = (int)(slab % ksteps) * SBK + (int)(in / (SBN * RUN)) * RUN;
       int u = 0;
-      while (u + 1 < G.nup && a.L.koff[u + 1] <= kk) ++u;
+      while (u + 1 < G.nup && a.L.koff[u + 1] <= kk0) ++u;  // a run lies in one level
       const Level &lv = G.lev[G.up[u]];
-      const int64_t k = kk - a.L.koff[u];
-      if (k < lv.tau) x = A[(int64_t)(lv.j0 + k) * a.lda + col];
+      const int k0 = kk0 - a.L.koff[u];
+      const bool cok = col < a.t;
+      const float *src = A + (int64_t)(lv.j0 + k0) * a.lda + (cok ? col : 0);
+#pragma unroll
+      for (int i = 0; i < RUN; ++i) x[i] = cok && k0 + i < lv.tau ? src[(int64_t)i * a.lda] : 0.f;
     }
-    const __bf16 h = (__bf16)x;
-    hi[e] = h;
-    lo[e] = (__bf16)(x - (float)h);
+    if constexpr (F32) {
+      f32x4v v;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) v[i] = x[i];
+      *reinterpret_cast<f32x4v *>(static_cast<float *>(out) + base + q0) = v;
+    } else {
+      bf16x8v h, l;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        h[i] = (__bf16)x[i];
+        l[i] = (__bf16)(x[i] - (float)h[i]);
+      }
+      __bf16 *hi = static_cast<__bf16 *>(out);
+      *reinterpret_cast<bf16x8v *>(hi + base + q0) = h;
+      *reinterpret_cast<bf16x8v *>(hi + a.half + base + q0) = l;
+    }
   }
 }
 
@@ -281,80 +340,180 @@ struct SplitGemmArgs {
   int32_t tile0[kMaxGemmProbs];
   int32_t nprob;
   float oscale;
-  int64_t a_rs, c_rs, ldc, kpad;
+  int64_t a_rs, c_rs, ldc, b_tile;  // b_tile: values of one column tile of the packed A (256 kpad)
   struct {
-    int32_t M, K, tiles_n;
+    int32_t M, ksteps, tiles_n;
     int64_t a_off, b_off, c_off;
   } p[kMaxLevels];
 };
 
-__global__ __launch_bounds__(256) void gemm_bf16x3(SplitGemmArgs g, int N, const __bf16 *__restrict__ Ahi,
-                                                   const __bf16 *__restrict__ Alo,
-                                                   const __bf16 *__restrict__ Bhi,
-                                                   const __bf16 *__restrict__ Blo, float *__restrict__ Cbase) {
-  __shared__ __attribute__((aligned(16))) __bf16 As[2][2][SBM * SRS];  // [buffer][hi, lo][row][k]
-  __shared__ __attribute__((aligned(16))) __bf16 Bs[2][2][SBN * SRS];  // [buffer][hi, lo][col][k]
-  const int r = blockIdx.y;
-  int tile = blockIdx.x;
-  int pi = 0;
+// Problem, row tile and column tile of this workgroup.
+struct TileRef {
+  int pi, tm, tn;
+};
+__device__ __forceinline__ TileRef tile_of(const SplitGemmArgs &g) {
+  int tile = blockIdx.x, pi = 0;
 #pragma unroll
   for (int q = 1; q < kMaxGemmProbs; ++q)
     if (tile >= g.tile0[q]) pi = q;
-  const auto &P = g.p[pi];
   tile -= g.tile0[pi];
-  const int tn = tile % P.tiles_n, tm = tile / P.tiles_n;
-  const int i0 = tm * SBM, j0 = tn * SBN;
+  return TileRef{pi, tile / g.p[pi].tiles_n, tile % g.p[pi].tiles_n};
+}
+
+// Epilogue: a wave's 16 x 128 block of output rows row0.. and columns col0..,
+// already in its LDS region E (row stride ES floats), stored as 512-byte row runs.
+// Columns up to ldc are written (past t the packed A is 0, so are they).
+template <int ES>
+__device__ __forceinline__ void store_rows(const float *E, float *C, int64_t ldc, int M, int row0, int col0,
+                                           float oscale, int lane) {
+#pragma unroll
+  for (int p = 0; p < 8; ++p) {
+    const int rr = 2 * p + (lane >> 5), cc = 4 * (lane & 31);
+    f32x4v v = *reinterpret_cast<const f32x4v *>(&E[rr * ES + cc]);
+    if (row0 + rr < M && col0 + cc < ldc)
+      __builtin_nontemporal_store(oscale * v, reinterpret_cast<f32x4v *>(&C[(int64_t)(row0 + rr) * ldc + col0 + cc]));
+  }
+}
+
+constexpr int ES32 = 132, ES16 = 136;  // epilogue row strides: the 16-row groups' writes on distinct banks
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void gemm_f32p(
+    SplitGemmArgs g, const float *__restrict__ Ap, const float *__restrict__ Bp, float *__restrict__ Cbase) {
+  __shared__ __attribute__((aligned(16))) float Ls[2 * (SLAB_A + SLAB_B)];  // [buffer][A slab, B slab]
+  static_assert(4 * 16 * ES32 <= 2 * (SLAB_A + SLAB_B), "epilogue does not fit");
+  const int r = blockIdx.y;
+  const TileRef T = tile_of(g);
+  const auto &P = g.p[T.pi];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int wr = (w >> 1) * 64, wc = (w & 1) * 64;
-  // loader: row (A) or column (B) ld = tid / 2, 8 K-values at kh = 8 (tid % 2)
-  const int ld = tid >> 1, kh = 8 * (tid & 1);
-  const int64_t aoff = r * g.a_rs + P.a_off;
-  const bool arow_ok = i0 + ld < P.M, bcol_ok = j0 + ld < N;
-  const __bf16 *ah_p = Ahi + aoff + (int64_t)(arow_ok ? i0 + ld : 0) * P.K + kh;
-  const __bf16 *al_p = Alo + aoff + (int64_t)(arow_ok ? i0 + ld : 0) * P.K + kh;
-  const __bf16 *bh_p = Bhi + P.b_off + (int64_t)(bcol_ok ? j0 + ld : 0) * g.kpad + kh;
-  const __bf16 *bl_p = Blo + P.b_off + (int64_t)(bcol_ok ? j0 + ld : 0) * g.kpad + kh;
-  bf16x8v ra[2], rb[2];
-  const bf16x8v zero = {};
-  auto load = [&](int k0) {
-    const bool kok = k0 + kh < P.K;  // K is a multiple of 8: a chunk is whole or absent
-    ra[0] = arow_ok && kok ? *reinterpret_cast<const bf16x8v *>(ah_p + k0) : zero;
-    ra[1] = arow_ok && kok ? *reinterpret_cast<const bf16x8v *>(al_p + k0) : zero;
-    rb[0] = bcol_ok && kok ? *reinterpret_cast<const bf16x8v *>(bh_p + k0) : zero;
-    rb[1] = bcol_ok && kok ? *reinterpret_cast<const bf16x8v *>(bl_p + k0) : zero;
+  const int wr = (w >> 1) * 64, wc = (w & 1) * 128;
+  const float *ap = Ap + r * g.a_rs + P.a_off + (int64_t)T.tm * P.ksteps * SLAB_A + tid * 4;
+  const float *bp = Bp + P.b_off + T.tn * g.b_tile + tid * 4;
+  f32x4v ra[2], rb[4];
+  auto load = [&](int ks) {
+    const int64_t ao = (int64_t)ks * SLAB_A, bo = (int64_t)ks * SLAB_B;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) ra[q] = *reinterpret_cast<const f32x4v *>(ap + ao + 1024 * q);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) rb[q] = *reinterpret_cast<const f32x4v *>(bp + bo + 1024 * q);
   };
   auto store = [&](int buf) {
+    float *As = Ls + buf * (SLAB_A + SLAB_B), *Bs = As + SLAB_A;
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      *reinterpret_cast<bf16x8v *>(&As[buf][h][ld * SRS + kh]) = ra[h];
-      *reinterpret_cast<bf16x8v *>(&Bs[buf][h][ld * SRS + kh]) = rb[h];
-    }
+    for (int q = 0; q < 2; ++q) *reinterpret_cast<f32x4v *>(&As[1024 * q + tid * 4]) = ra[q];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) *reinterpret_cast<f32x4v *>(&Bs[1024 * q + tid * 4]) = rb[q];
   };
-  f32x16 acc[2][2];
+  f32x4v acc[4][8];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = f32x16{0};
+    for (int j = 0; j < 8; ++j) acc[i][j] = f32x4v{0.f, 0.f, 0.f, 0.f};
   load(0);
   store(0);
   __syncthreads();
   int cur = 0;
-  const int ko = 8 * (lane >> 5);  // this lane's K-values of a step: ko .. ko + 7
-  for (int k0 = 0; k0 < P.K; k0 += SBK) {
-    const bool more = k0 + SBK < P.K;
-    if (more) load(k0 + SBK);
-    bf16x8v xa[2][2], xb[2][2];  // [block][hi, lo]
+  // fragment offsets: row (column) wr + 16 i + lane % 16, k = 4 (lane / 16) .. + 3
+  const int fa = (lane >> 4) * (SBM * 4) + (wr + (lane & 15)) * 4;
+  const int fb = (lane >> 4) * (SBN * 4) + (wc + (lane & 15)) * 4;
+  for (int ks = 0; ks < P.ksteps; ++ks) {
+    const bool more = ks + 1 < P.ksteps;
+    if (more) load(ks + 1);
+    const float *As = Ls + cur * (SLAB_A + SLAB_B), *Bs = As + SLAB_A;
+    f32x4v xa[4], xb[8];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) xa[i] = *reinterpret_cast<const f32x4v *>(&As[fa + 64 * i]);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) xb[j] = *reinterpret_cast<const f32x4v *>(&Bs[fb + 64 * j]);
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[i][c], xb[j][c], acc[i][j], 0, 0, 0);
+    if (more) store(cur ^ 1);
+    __syncthreads();
+    cur ^= 1;
+  }
+  // D of a 16 x 16 block: acc[v] at row 4 (lane / 16) + v, column lane % 16
+  float *E = Ls + w * 16 * ES32;
+  float *Cb = Cbase + r * g.c_rs + P.c_off;
+  const int i0 = T.tm * SBM + wr, j0 = T.tn * SBN + wc;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) E[(4 * (lane >> 4) + v) * ES32 + 16 * j + (lane & 15)] = acc[i][j][v];
+    __syncthreads();
+    store_rows<ES32>(E, Cb, g.ldc, P.M, i0 + 16 * i, j0, g.oscale, lane);
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void gemm_bf16x3(
+    SplitGemmArgs g, const __bf16 *__restrict__ Ahi, const __bf16 *__restrict__ Alo,
+    const __bf16 *__restrict__ Bhi, const __bf16 *__restrict__ Blo, float *__restrict__ Cbase) {
+  __shared__ __attribute__((aligned(16))) __bf16 Ls[2 * 2 * (SLAB_A + SLAB_B)];  // [buffer][hi, lo][A, B slab]
+  static_assert(4 * 16 * ES16 * 4 <= 2 * 2 * (SLAB_A + SLAB_B) * 2, "epilogue does not fit");
+  const int r = blockIdx.y;
+  const TileRef T = tile_of(g);
+  const auto &P = g.p[T.pi];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wr = (w >> 1) * 64, wc = (w & 1) * 128;
+  // this thread's 16-byte chunks of each slab: A chunk tid, B chunks tid and tid + 256
+  const int64_t aoff = r * g.a_rs + P.a_off + (int64_t)T.tm * P.ksteps * SLAB_A + tid * 8;
+  const int64_t boff = P.b_off + T.tn * g.b_tile + tid * 8;
+  const __bf16 *ah_p = Ahi + aoff, *al_p = Alo + aoff, *bh_p = Bhi + boff, *bl_p = Blo + boff;
+  bf16x8v ra[2], rb[2][2];
+  auto load = [&](int ks) {
+    const int64_t ao = (int64_t)ks * SLAB_A, bo = (int64_t)ks * SLAB_B;
+    ra[0] = *reinterpret_cast<const bf16x8v *>(ah_p + ao);
+    ra[1] = *reinterpret_cast<const bf16x8v *>(al_p + ao);
+    rb[0][0] = *reinterpret_cast<const bf16x8v *>(bh_p + bo);
+    rb[0][1] = *reinterpret_cast<const bf16x8v *>(bh_p + bo + SLAB_B / 2);
+    rb[1][0] = *reinterpret_cast<const bf16x8v *>(bl_p + bo);
+    rb[1][1] = *reinterpret_cast<const bf16x8v *>(bl_p + bo + SLAB_B / 2);
+  };
+  // buffer b, h = hi / lo: A slab at (2 b + h) (SLAB_A + SLAB_B), its B slab SLAB_A further
+  auto slab = [&](int buf, int h) { return Ls + (2 * buf + h) * (SLAB_A + SLAB_B); };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      __bf16 *As = slab(buf, h), *Bs = As + SLAB_A;
+      *reinterpret_cast<bf16x8v *>(&As[tid * 8]) = ra[h];
+      *reinterpret_cast<bf16x8v *>(&Bs[tid * 8]) = rb[h][0];
+      *reinterpret_cast<bf16x8v *>(&Bs[SLAB_B / 2 + tid * 8]) = rb[h][1];
+    }
+  };
+  f32x16 acc[2][4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f32x16{0};
+  load(0);
+  store(0);
+  __syncthreads();
+  int cur = 0;
+  // fragment offsets inside a slab: row (or column) wr + 32 i + lane % 32 at k-half lane / 32
+  const int fa = (lane >> 5) * (SBM * 8) + (wr + (lane & 31)) * 8;
+  const int fb = (lane >> 5) * (SBN * 8) + (wc + (lane & 31)) * 8;
+  for (int ks = 0; ks < P.ksteps; ++ks) {
+    const bool more = ks + 1 < P.ksteps;
+    if (more) load(ks + 1);
+    bf16x8v xa[2][2], xb[4][2];  // [block][hi, lo]
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const __bf16 *As = slab(cur, h), *Bs = As + SLAB_A;
+#pragma unroll
+      for (int i = 0; i < 2; ++i) xa[i][h] = *reinterpret_cast<const bf16x8v *>(&As[fa + 256 * i]);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) xb[j][h] = *reinterpret_cast<const bf16x8v *>(&Bs[fb + 256 * j]);
+    }
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        xa[i][h] = *reinterpret_cast<const bf16x8v *>(&As[cur][h][(wr + 32 * i + (lane & 31)) * SRS + ko]);
-        xb[i][h] = *reinterpret_cast<const bf16x8v *>(&Bs[cur][h][(wc + 32 * i + (lane & 31)) * SRS + ko]);
-      }
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
+      for (int j = 0; j < 4; ++j) {
         acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xa[i][1], xb[j][0], acc[i][j], 0, 0, 0);
         acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xa[i][0], xb[j][1], acc[i][j], 0, 0, 0);
         acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xa[i][0], xb[j][0], acc[i][j], 0, 0, 0);
@@ -363,62 +522,80 @@ __global__ __launch_bounds__(256) void gemm_bf16x3(SplitGemmArgs g, int N, const
     __syncthreads();
     cur ^= 1;
   }
+  // D of a 32 x 32 block: acc[v] at row 8 (v / 4) + 4 (lane / 32) + v % 4, column lane % 32;
+  // v < 8 are its rows 0..15, v >= 8 its rows 16..31
+  float *E = reinterpret_cast<float *>(Ls) + w * 16 * ES16;
   float *Cb = Cbase + r * g.c_rs + P.c_off;
+  const int i0 = T.tm * SBM + wr, j0 = T.tn * SBN + wc;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int col = j0 + wc + 32 * j + (lane & 31);
+    for (int hf = 0; hf < 2; ++hf) {
 #pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const int row = i0 + wr + 32 * i + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-        if (row < P.M && col < N)
-          __builtin_nontemporal_store(g.oscale * acc[i][j][v], &Cb[(int64_t)row * g.ldc + col]);
-      }
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int v = 0; v < 8; ++v)
+          E[(8 * (v >> 2) + 4 * (lane >> 5) + (v & 3)) * ES16 + 32 * j + (lane & 31)] = acc[i][j][8 * hf + v];
+      __syncthreads();
+      store_rows<ES16>(E, Cb, g.ldc, P.M, i0 + 32 * i + 16 * hf, j0, g.oscale, lane);
+      __syncthreads();
     }
 }
 
-static hipError_t launch_levels_split(const Geometry &G, const float *tables, int nr, const float *A, int t,
-                                      int64_t lda, float *U, int64_t ldu, float oscale, void *bsplit,
-                                      hipStream_t st) {
-  const SplitLayout L = split_layout(G);
-  __bf16 *hi = static_cast<__bf16 *>(bsplit);
-  const int64_t half = (int64_t)nr * L.up_pad + L.kpad * (int64_t)t;  // elements per hi / lo array
-  __bf16 *lo = hi + half;
+static hipError_t launch_levels_packed(const Geometry &G, int prec, const float *tables, int nr, const float *A,
+                                       int t, int64_t lda, float *U, int64_t ldu, float oscale, void *buf,
+                                       hipStream_t st) {
+  const SplitLayout L = split_layout(G, t);
+  const int64_t ntab = (int64_t)nr * L.up_pad;
   SplitArgs sa;
   sa.G = G;
   sa.L = L;
   sa.nr = nr;
   sa.t = t;
   sa.lda = lda;
-  const int64_t blocks = std::min<int64_t>(ceil_div(half, 256), 16384);
-  hipLaunchKernelGGL(split_kernel, dim3((unsigned)blocks), dim3(256), 0, st, sa, tables, A, hi, lo);
+  sa.half = packed_values(L, nr);
+  const bool f32 = prec == QMC_FP32;
+  const int run = f32 ? 4 : 8;
+  const int64_t truns = L.up_pad / run, aruns = (int64_t)L.ntn * SBN * L.kpad / run;
+  const auto pack = f32 ? pack_kernel<true> : pack_kernel<false>;
+  if (nr > 0 && truns > 0)
+    hipLaunchKernelGGL(pack, dim3((unsigned)std::min<int64_t>(ceil_div(truns, 256), 1024), nr), dim3(256), 0, st,
+                       sa, true, tables, A, buf);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(pack, dim3((unsigned)std::min<int64_t>(ceil_div(aruns, 256), 4096)), dim3(256), 0, st, sa,
+                     false, tables, A, buf);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   SplitGemmArgs g{};
   g.nprob = G.nup;
   g.oscale = oscale;
   g.a_rs = L.up_pad;
   g.c_rs = G.urows * ldu;
   g.ldc = ldu;
-  g.kpad = L.kpad;
+  g.b_tile = (int64_t)SBN * L.kpad;
   int tiles = 0;
   for (int u = 0; u < G.nup; ++u) {
     const Level &lv = G.lev[G.up[u]];
     auto &P = g.p[u];
     P.M = 1 << lv.nb;
-    P.K = L.taup[u];
-    P.tiles_n = (int)ceil_div(t, SBN);
+    P.ksteps = L.taup[u] / SBK;
+    P.tiles_n = L.ntn;
     P.a_off = L.tab_off[u];
-    P.b_off = (int64_t)nr * L.up_pad + L.koff[u];
+    P.b_off = ntab + (int64_t)(L.koff[u] / SBK) * SLAB_B;
     P.c_off = lv.uoff * ldu;
     g.tile0[u] = tiles;
-    tiles += (int)ceil_div(P.M, SBM) * P.tiles_n;
+    tiles += L.tiles_m[u] * P.tiles_n;
   }
   for (int q = G.nup; q < kMaxGemmProbs; ++q) g.tile0[q] = 0x7fffffff;
   if (tiles == 0 || nr == 0) return hipSuccess;
-  // B (the split A^T) lives after the tables in both arrays: its offset is in b_off
-  hipLaunchKernelGGL(gemm_bf16x3, dim3(tiles, nr), dim3(256), 0, st, g, t, hi, lo, hi, lo, U);
+  // the packed A follows the tables: its offset is in b_off
+  if (f32) {
+    const float *p = static_cast<const float *>(buf);
+    hipLaunchKernelGGL(gemm_f32p, dim3(tiles, nr), dim3(256), 0, st, g, p, p, U);
+  } else {
+    const __bf16 *hi = static_cast<const __bf16 *>(buf), *lo = hi + sa.half;
+    hipLaunchKernelGGL(gemm_bf16x3, dim3(tiles, nr), dim3(256), 0, st, g, hi, lo, hi, lo, U);
+  }
   return hipGetLastError();
 }
 
@@ -435,40 +612,11 @@ static hipError_t run_gemm(const GemmArgs &a, int prec, int nr, const float *A, 
 }
 
 hipError_t launch_levels(const Geometry &G, int prec, const float *tables, int nr, const float *A,
-                         int t, int64_t lda, float *U, int64_t ldu, float oscale, void *bsplit, hipStream_t st) {
+                         int t, int64_t lda, float *U, int64_t ldu, float oscale, void *pack, hipStream_t st) {
   LaunchTimer tm("levels", st);
-  if (prec == QMC_SPLIT_BF16X3 && bsplit && G.nup > 0)
-    return launch_levels_split(G, tables, nr, A, t, lda, U, ldu, oscale, bsplit, st);
-  GemmArgs a = {};
-  a.oscale = oscale;
-  a.a_rs = G.table_total;
-  a.b_rs = 0;
-  a.c_rs = G.urows * ldu;
-  a.ldb = lda;
-  a.ldc = ldu;
-  int tiles = 0;
-  for (int u = 0; u < G.nup; ++u) {
-    const Level &L = G.lev[G.up[u]];
-    GemmProb &P = a.p[a.nprob++];
-    P.M = 1 << L.nb;
-    P.N = t;
-    P.K = L.tau;
-    P.tiles_m = (int)ceil_div(P.M, BM);
-    P.tiles_n = (int)ceil_div(t, BN);
-    P.kchunk = (int)round_up(P.K, BK);
-    P.kchunks = 1;
-    P.tile0 = tiles;
-    P.a_off = G.lower_total + L.off;
-    P.a_si = L.tau;
-    P.a_sk = 1;
-    P.b_off = (int64_t)L.j0 * lda;
-    P.c_off = L.uoff * ldu;
-    P.c_chunk = 0;
-    tiles += P.tiles_m * P.tiles_n;
-  }
-  a.total_tiles = tiles;
-  finish_tile_table(a);
-  return run_gemm<false>(a, prec, nr, tables, A, U, st);
+  if (G.nup == 0 || nr == 0) return hipSuccess;
+  if (!pack || ldu % 4 != 0) return hipErrorInvalidValue;
+  return launch_levels_packed(G, prec, tables, nr, A, t, lda, U, ldu, oscale, pack, st);
 }
 
 // Adjoint partial layout: for each upper level (in order) kchunks blocks of

@@ -165,11 +165,11 @@ hipError_t launch_point_matrix(const Geometry &G, const DevSpec &D, int r, float
                                hipStream_t st);
 
 // Grouped upper-level products U_I = oscale X~_I A_I for shifts [0, nr) of the table buffer.
-// Split BF16 with bsplit (levels_split_bytes(G, nr, t) bytes, 16-byte aligned):
-// the operands are split into (hi, lo) there once, then multiplied; without it
-// they are split inside the product loop.
+// pack (levels_split_bytes(G, nr, t) bytes, 16-byte aligned) receives the
+// operands packed into K-step slabs (split BF16: split into hi and lo) once,
+// then multiplied; ldu is a multiple of 4.
 hipError_t launch_levels(const Geometry &G, int prec, const float *tables, int nr, const float *A,
-                         int t, int64_t lda, float *U, int64_t ldu, float oscale, void *bsplit, hipStream_t st);
+                         int t, int64_t lda, float *U, int64_t ldu, float oscale, void *pack, hipStream_t st);
 int64_t levels_split_bytes(const Geometry &G, int nr, int t);
 
 // Adjoint of the upper levels: dA_I = X~_I^T S_I; S pyramid rows as in fold.
