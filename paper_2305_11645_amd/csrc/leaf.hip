@@ -223,6 +223,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
   // own subtrees; lane column q is ct CW + q 64 + lane
   const int bx = blockIdx.x, ct = blockIdx.y, rl = blockIdx.z;
   const int col = ct * CW + lane;
+  // Storing mode: a lane past column t does the last column's work and stores
+  // the same values to the same addresses, so the stores need no branch (a
+  // branch around them would keep the prefetch below from overlapping them).
+  const int lcol = MODE == kModeStoreY && col >= a.t ? a.t - 1 - ct * CW : lane;
   bool live[CPL];
 #pragma unroll
   for (int q = 0; q < CPL; ++q) live[q] = col + q * kTileT < a.t;
@@ -283,24 +287,43 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
   // (balanced: the first sub_rem workgroups take sub_per + 1 subtrees)
   const int first = bx * a.sub_per + min(bx, a.sub_rem);
   const int last = first + a.sub_per + (bx < a.sub_rem ? 1 : 0);
+  // subtree root: the upper levels' rows, requested RB at a time
+  constexpr int RB = MODE == kModeSum || MODE == kModeStoreY ? kRootBatch : 1;
+  auto root_batch = [&](int rho, int u0, float (&rv)[RB][CPL]) {
+#pragma unroll
+    for (int i = 0; i < RB; ++i) {  // entries past nup are zero: they read row 0
+      // uniform row address (scalar unit), then this lane's column
+      const float *row = Ub + a.up_off[u0 + i] + (uint64_t)(uint32_t)(rho & a.up_mask[u0 + i]) * a.ldu32;
+#pragma unroll
+      for (int q = 0; q < CPL; ++q) rv[i][q] = row[ct * CW + lcol + q * kTileT];
+    }
+  };
+  // Storing mode: the first root batch of the wave's next subtree is requested
+  // before this subtree's rows of Y are stored, so waiting for it does not
+  // wait for those stores too (one vector memory counter covers both).  The
+  // wave's first subtree loads its own.
+  float rvn[RB][CPL];
   for (int rho = first + w; rho < last; rho += a.nw) {
     const float *rec = tab + (int64_t)rho * a.rec;
 
-    // subtree root: the upper levels' rows, requested RB at a time
-    constexpr int RB = MODE == kModeSum ? kRootBatch : 1;
     float root[CPL];
 #pragma unroll
     for (int q = 0; q < CPL; ++q) root[q] = 0.f;
+    int ubeg = 0;
+    if (MODE == kModeStoreY && rho != first + w) {
+#pragma unroll
+      for (int i = 0; i < RB; ++i)
+#pragma unroll
+        for (int q = 0; q < CPL; ++q) {
+          asm volatile("" ::"v"(rvn[i][q]));
+          if (i < a.nup) root[q] += rvn[i][q];
+        }
+      ubeg = RB;
+    }
 #pragma unroll 1
-    for (int u0 = 0; u0 < a.nup; u0 += RB) {
+    for (int u0 = ubeg; u0 < a.nup; u0 += RB) {
       float rv[RB][CPL];
-#pragma unroll
-      for (int i = 0; i < RB; ++i) {  // entries past nup are zero: they read row 0
-        // uniform row address (scalar unit), then this lane's column
-        const float *row = Ub + a.up_off[u0 + i] + (uint64_t)(uint32_t)(rho & a.up_mask[u0 + i]) * a.ldu32;
-#pragma unroll
-        for (int q = 0; q < CPL; ++q) rv[i][q] = row[col + q * kTileT];
-      }
+      root_batch(rho, u0, rv);
 #pragma unroll
       for (int i = 0; i < RB; ++i)
 #pragma unroll
@@ -344,6 +367,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
 #pragma unroll
       for (int q = 0; q < CPL; ++q)
         if (live[q]) acc += (double)s[q];
+    } else if constexpr (MODE == kModeStoreY) {
+      // the lean descent of the summing mode, then the 64 rows of Y
+      uint64_t taus = a.taus;
+      asm volatile("" : "+s"(taus));
+      int xo = 0, j0 = jlow;
+      float y[1][NL];
+      y[0][0] = root[0];
+      descend_lean<LP, LP - 1, 0, 1>(y, rec, xo, j0, taus, Alds + lcol);
+      if (a.nup > 0 && rho + a.nw < last) root_batch(rho + a.nw, 0, rvn);
+#pragma unroll
+      for (int c = 0; c < NL; ++c) Y[((int64_t)rho + (int64_t)c * a.nsub) * a.ldy + ct * CW + lcol] = y[0][c];
     } else {
       float y[NL];
       y[0] = root[0];
@@ -355,11 +389,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
         for (int c = 0; c < 64; ++c) v[c] = (c < NL && live0) ? g_val<GF>(y[c < NL ? c : 0]) : 0.f;
         transpose_step<32>(v, lane);
         if (lane < NL) ppart[(((int64_t)rl * a.tct + ct) * a.nsub + rho) * NL + lane] = v[0];
-      } else if (MODE == kModeStoreY) {
-        if (live0) {
-#pragma unroll
-          for (int c = 0; c < NL; ++c) Y[((int64_t)rho + (int64_t)c * a.nsub) * a.ldy + col] = y[c];
-        }
       } else {  // kModeGrad
         float S[NL];
         float s = 0.f;

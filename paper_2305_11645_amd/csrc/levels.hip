@@ -573,17 +573,23 @@ static hipError_t launch_levels_packed(const Geometry &G, int prec, const float 
   g.c_rs = G.urows * ldu;
   g.ldc = ldu;
   g.b_tile = (int64_t)SBN * L.kpad;
+  // problems in decreasing K: the longest tiles are dispatched first and the
+  // short ones fill the tail
+  int order[kMaxLevels];
+  for (int u = 0; u < G.nup; ++u) order[u] = u;
+  std::stable_sort(order, order + G.nup, [&](int x, int y) { return L.taup[x] > L.taup[y]; });
   int tiles = 0;
-  for (int u = 0; u < G.nup; ++u) {
+  for (int q = 0; q < G.nup; ++q) {
+    const int u = order[q];
     const Level &lv = G.lev[G.up[u]];
-    auto &P = g.p[u];
+    auto &P = g.p[q];
     P.M = 1 << lv.nb;
     P.ksteps = L.taup[u] / SBK;
     P.tiles_n = L.ntn;
     P.a_off = L.tab_off[u];
     P.b_off = ntab + (int64_t)(L.koff[u] / SBK) * SLAB_B;
     P.c_off = lv.uoff * ldu;
-    g.tile0[u] = tiles;
+    g.tile0[q] = tiles;
     tiles += L.tiles_m[u] * P.tiles_n;
   }
   for (int q = G.nup; q < kMaxGemmProbs; ++q) g.tile0[q] = 0x7fffffff;
