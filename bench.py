@@ -323,7 +323,7 @@ def bench_grad(args, wl) -> int:
     if "adjoint" in kern:
         # the adjoint products: 2 N jlow t R flops over all points, plus
         # 2 n_split (s - jlow) t R over the folded upper coordinates (base b > 2)
-        L = pts.split_level
+        L = pts.grad_split_level
         jlow = wl.s if L < 0 else int(np.sum(np.minimum(wl.w, wl.m) < L))
         nsplit = wl.b ** (wl.m - L) if L >= 0 else 0
         mf = 2.0 * wl.t * wl.R * (wl.N * jlow + nsplit * (wl.s - jlow)) * (3 if prec == 1 else 1)
@@ -336,7 +336,7 @@ def bench_grad(args, wl) -> int:
     elif "leaf_grad" in kern:
         # the tree path: the gradient-mode leaf pass is the dominant kernel
         lms = kern["leaf_grad"]["ms_per_step"] * args.steps / kern["leaf_grad"]["launches"]
-        slots = grad_leaf_algorithmic_slots(wl, pts.split_level)
+        slots = grad_leaf_algorithmic_slots(wl, pts.grad_split_level)
         roofline = alu_roofline("grad_kernel (leaf, gradient mode)", 2 * slots / (lms * 1e-3) / 1e12, slots, lms,
                                 leaf_traffic(args.config, "grad", kernel="grad_kernel"))
     flops = 4.0 * wl.N * wl.s * wl.t * wl.R
@@ -344,7 +344,7 @@ def bench_grad(args, wl) -> int:
            "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 5),
            "higher_is_better": True, "dtype": "f32" if prec == 0 else "bf16x3", "data": "synthetic",
            "config": {"workload": f"C{args.config}", "N": wl.N, "s": wl.s, "t": wl.t, "R": wl.R, "b": wl.b,
-                      "split_level": pts.split_level},
+                      "split_level": pts.grad_split_level},
            "roofline": roofline, "kernels": kern}
     calibrate_copy(args.calibrate_copy_mib)
     print(json.dumps(out), flush=True)

@@ -182,6 +182,14 @@ qmc_status qmc_points_free(qmc_points p);
 qmc_status qmc_points_info(qmc_points p, int64_t *N, int32_t *s, int32_t *R, int32_t *split_level,
                            int64_t *distinct_values);
 
+/* The split level L' of the gradient (qmc_estimate_grad; Section 3's
+ * transposed cascade): the estimate's, capped at 5.  Levels at and above it
+ * go to the matrix-core products, the lower ones to the fused leaf pass, whose
+ * gradient form holds a subtree's leaves and one accumulator per lower
+ * coordinate in registers: with 32 leaves per subtree it keeps four waves per
+ * SIMD.  -1 as for qmc_points_info.  EINVAL: p or split_level null. */
+qmc_status qmc_points_grad_split(qmc_points p, int32_t *split_level);
+
 /*
  * Distinct values X_j[rho], rho < n_j, of coordinate j for randomisation r, in
  * FP64 after shift and map (Section 2.1 X_j; Section 2.3 maps).  out: device,

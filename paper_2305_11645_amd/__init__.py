@@ -80,6 +80,9 @@ class Points:
         N, s_, R_, sp, dv = ct.c_int64(), ct.c_int32(), ct.c_int32(), ct.c_int32(), ct.c_int64()
         check(L.qmc_points_info(h, ct.byref(N), ct.byref(s_), ct.byref(R_), ct.byref(sp), ct.byref(dv)))
         self.split_level = sp.value
+        gs = ct.c_int32()
+        check(L.qmc_points_grad_split(h, ct.byref(gs)))
+        self.grad_split_level = gs.value  # the gradient's (capped at 5)
         self.distinct_values = dv.value
         self.device = _torch().cuda.current_device()
 

@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(HERE, "libqmcred.so")
 
 # every symbol include/qmcred.h declares
 EXPORTS = [
-    "qmc_points_init", "qmc_points_free", "qmc_points_info", "qmc_point_values",
+    "qmc_points_init", "qmc_points_free", "qmc_points_info", "qmc_points_grad_split", "qmc_point_values",
     "qmc_point_matrix", "qmc_workspace_size", "qmc_reduced_matvec", "qmc_estimate",
     "qmc_estimate_static",
     "qmc_estimate_grad", "qmc_status_string", "qmc_last_error", "qmc_timing_enable",
@@ -57,6 +57,7 @@ def load() -> ct.CDLL:
     L.qmc_points_free.argtypes = [vp]
     L.qmc_points_info.argtypes = [vp, ct.POINTER(i64), ct.POINTER(i32), ct.POINTER(i32),
                                   ct.POINTER(i32), ct.POINTER(i64)]
+    L.qmc_points_grad_split.argtypes = [vp, ct.POINTER(i32)]
     L.qmc_point_values.argtypes = [vp, i32, i32, vp, vp]
     L.qmc_point_matrix.argtypes = [vp, i32, vp, i64, vp]
     L.qmc_workspace_size.argtypes = [vp, i32, i32, ct.POINTER(Integrand), i32, ct.POINTER(sz)]

@@ -13,7 +13,8 @@ namespace qmc {
 // accumulator per lower coordinate and its column in registers (2^{L'} - 1
 // of them, indexed at compile time by level and position in the level), so
 // the transposed recursion needs no LDS traffic per subtree, and a workgroup
-// only stages its rows of A: four waves per workgroup and four per SIMD.
+// only stages its rows of A: four waves per workgroup and, with L' <= 5 (at
+// most 31 accumulators and 32 leaves per lane), five per SIMD.
 // Per subtree: the forward descent of the summing mode to the level-1 nodes,
 // then level 0 fused with the integrand (leaves c and c + 2^{L'-1} of node c:
 // their sensitivities G'_k, the level-0 product, and their sum as the node's
@@ -123,11 +124,11 @@ __device__ __forceinline__ void leaf_grad_block(float (&y)[1 << LP], const float
 }
 
 template <int LP, int GF, bool HD>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void grad_kernel(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void grad_kernel(
     LeafArgs a, const float *__restrict__ tables, const float *__restrict__ U, const float *__restrict__ A,
     double *__restrict__ partial, float *__restrict__ dApart, float *__restrict__ Sroot,
     const float *__restrict__ hd) {
-  static_assert(LP >= 1 && LP <= kMaxSplit, "register adjoint needs 1 <= L' <= 6");
+  static_assert(LP >= 1 && LP <= kMaxSplitGrad, "register adjoint needs 1 <= L' <= kMaxSplitGrad");
   constexpr int NL = 1 << LP;
   extern __shared__ float smem[];
   __shared__ double red[8];
@@ -172,7 +173,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void g
 
   const float *tab = tables + (int64_t)rl * a.tstride;
   const float *Ub = U + (int64_t)rl * a.ustride;
-  float d0 = 0.f, d1[2], d2[4], d3[8], d4[16], d5[32];
+  float d0 = 0.f, d1[2], d2[4], d3[8], d4[16];
 #pragma unroll
   for (int i = 0; i < 2; ++i) d1[i] = 0.f;
 #pragma unroll
@@ -181,8 +182,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void g
   for (int i = 0; i < 8; ++i) d3[i] = 0.f;
 #pragma unroll
   for (int i = 0; i < 16; ++i) d4[i] = 0.f;
-#pragma unroll
-  for (int i = 0; i < 32; ++i) d5[i] = 0.f;
   double acc = 0.0;
 
   const int first = bx * a.sub_per + min(bx, a.sub_rem);
@@ -240,11 +239,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void g
       xl -= tau * (NL >> 4);
       ascend_reg<LP, 4>(y[0], rec + xl, tau, d4);
     }
-    if constexpr (LP > 5) {
-      const int tau = (int)((taus >> 40) & 0xff);
-      xl -= tau * (NL >> 5);
-      ascend_reg<LP, 5>(y[0], rec + xl, tau, d5);
-    }
     if (live) {
       Sroot[((int64_t)rl * 2 * a.nsub + rho) * a.ldu + col] = y[0][0];
       if (!HD) acc += (double)s;
@@ -287,7 +281,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void g
       if constexpr (LP > 2) put(d2, 2);
       if constexpr (LP > 3) put(d3, 3);
       if constexpr (LP > 4) put(d4, 4);
-      if constexpr (LP > 5) put(d5, 5);
     }
   }
   __syncthreads();
@@ -299,7 +292,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void g
 // Whether the register form of the adjoint applies: 1 <= L' and tau_I <= 2^I
 // for every lower level.
 bool grad_reg_ok(const Geometry &G) {
-  if (G.split < 1 || G.split > kMaxSplit) return false;
+  if (G.split < 1 || G.split > kMaxSplitGrad) return false;
   for (int I = 0; I < G.split; ++I)
     if (G.lev[I].tau > (1 << I)) return false;
   if (getenv("QMC_GRAD_GENERIC")) return false;  // measurement switch: the LDS form
@@ -322,8 +315,7 @@ const void *grad_fn(const Geometry &G, int gf, bool hd) {
     case 2: return grad_fn_lp<2>(gf, hd);
     case 3: return grad_fn_lp<3>(gf, hd);
     case 4: return grad_fn_lp<4>(gf, hd);
-    case 5: return grad_fn_lp<5>(gf, hd);
-    default: return grad_fn_lp<6>(gf, hd);
+    default: return grad_fn_lp<5>(gf, hd);  // the gradient's split level is at most kMaxSplitGrad
   }
 }
 

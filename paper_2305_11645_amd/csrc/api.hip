@@ -14,7 +14,8 @@
 
 struct qmc_points_s {
   int device = 0;
-  qmc::Geometry G{};
+  qmc::Geometry G{};   // the estimate's and the matrix-vector product's
+  qmc::Geometry Gg{};  // the gradient's: the split level capped at kMaxSplitGrad
   qmc::DevSpec D{};
   void *d_gen = nullptr, *d_nb = nullptr, *d_shift = nullptr, *d_dshift = nullptr;
   void *d_samples = nullptr, *d_soff = nullptr;
@@ -69,8 +70,8 @@ bool is_prime(int b) {
   return true;
 }
 
-// Split level L' and record/table layout (see qmc_internal.h).
-void plan_geometry(qmc::Geometry &G, const int32_t *w) {
+// Split level L' (at most max_split) and record/table layout (see qmc_internal.h).
+void plan_geometry(qmc::Geometry &G, const int32_t *w, int max_split) {
   using namespace qmc;
   const int m = G.m;
   for (int I = 0; I <= m; ++I) {
@@ -88,7 +89,7 @@ void plan_geometry(qmc::Geometry &G, const int32_t *w) {
     if (G.lev[I].j0 < 0) G.lev[I].j0 = jcur;
     jcur = G.lev[I].j0 + G.lev[I].tau;
   }
-  int split = m < kMaxSplit ? m : kMaxSplit;
+  int split = m < max_split ? m : max_split;
   if (const char *env = getenv("QMC_SPLIT_LEVEL")) {
     const int v = atoi(env);
     if (v >= 0 && v <= split) split = v;
@@ -524,7 +525,9 @@ qmc_status qmc_points_init(qmc_points *out, const qmc_point_spec *sp) {
   G.R = sp->R;
   G.b = b;
   G.nonperiodic = nonperiodic ? 1 : 0;
-  plan_geometry(G, sp->w);
+  p->Gg = G;
+  plan_geometry(G, sp->w, kMaxSplit);
+  plan_geometry(p->Gg, sp->w, kMaxSplitGrad);
   // the cascade below is planned in base 2; a base b > 2 takes the gather path
   G.gather = nonperiodic || b != 2 ? 1 : 0;
   if (nonperiodic) {  // one pass over every coordinate and point
@@ -536,6 +539,7 @@ qmc_status qmc_points_init(qmc_points *out, const qmc_point_spec *sp) {
     plan_gather_split(G, sp->w, Nb);
   }
   G.gather_total = gather_total;
+  if (G.gather) p->Gg = G;  // the gathered path plans one layout for every operation
 
   auto cleanup = [&](qmc_status st) {
     qmc_points_free(p);
@@ -639,6 +643,13 @@ qmc_status qmc_points_info(qmc_points p, int64_t *N, int32_t *s, int32_t *R, int
   return QMC_OK;
 }
 
+qmc_status qmc_points_grad_split(qmc_points p, int32_t *split_level) {
+  if (qmc_status st = check_points(p)) return st;
+  if (!split_level) return fail(QMC_EINVAL, "split_level is null");
+  *split_level = p->Gg.gather && p->Gg.jlow == p->Gg.s ? -1 : p->Gg.split;
+  return QMC_OK;
+}
+
 qmc_status qmc_point_values(qmc_points p, int32_t r, int32_t j, double *out, void *stream) {
   if (qmc_status st = check_points(p)) return st;
   if (r < 0 || r >= p->G.R) return fail(QMC_EINVAL, "r = %d outside [0, %d)", r, p->G.R);
@@ -674,7 +685,7 @@ qmc_status qmc_workspace_size(qmc_points p, int32_t op, int32_t t, const qmc_int
   }
   DeviceGuard dg(p->device);  // the leaf plan queries the device's occupancy
   Work wk;
-  *bytes = carve(p->G, op, t, f, op == kOpMatvec ? 1 : p->G.R, prec, nullptr, wk);
+  *bytes = carve(op == kOpGrad ? p->Gg : p->G, op, t, f, op == kOpMatvec ? 1 : p->G.R, prec, nullptr, wk);
   return QMC_OK;
 }
 
@@ -819,7 +830,7 @@ static qmc_status estimate_impl(qmc_points p, const float *A, int32_t t, int64_t
   const bool grad = dA != nullptr;
   DeviceGuard dg(p->device);
   hipStream_t st = (hipStream_t)stream;
-  const Geometry &G = p->G;
+  const Geometry &G = grad ? p->Gg : p->G;
   const int nr = G.R;
   const int op = grad ? kOpGrad : kOpEstimate;
   Work wk;

@@ -518,7 +518,9 @@ static const void *leaf_fn_m(int mode, bool fuse0, int gf, int cpl) {
     case kModeSum: return leaf_fn_f<LP, kModeSum>(fuse0, gf, cpl);
     case kModePoint: return leaf_fn_f<LP, kModePoint>(fuse0, gf, cpl);
     case kModeStoreY: return leaf_fn_f<LP, kModeStoreY>(fuse0, gf, cpl);
-    default: return leaf_fn_f<LP, kModeGrad>(fuse0, gf, cpl);
+    default:  // the gradient's split level is at most kMaxSplitGrad
+      if constexpr (LP <= kMaxSplitGrad) return leaf_fn_f<LP, kModeGrad>(fuse0, gf, cpl);
+      else return nullptr;
   }
 }
 
@@ -624,6 +626,7 @@ hipError_t launch_leaf(const Geometry &G, int mode, const qmc_integrand &f, cons
   }
   const size_t lds = leaf_lds_bytes(G, mode, lp.cpl, lp.nw);
   const void *fn = leaf_fn(G, mode, f.g, lp.cpl);
+  if (!fn) return hipErrorInvalidDeviceFunction;
   void *args[] = {&a, (void *)&tables, (void *)&U, (void *)&A, (void *)&o.partial, (void *)&o.ppart,
                   (void *)&o.Y, (void *)&o.dApart, (void *)&o.Sroot, (void *)&o.hd};
   const hipError_t e = hipLaunchKernel(fn, grid, block, args, lds, st);

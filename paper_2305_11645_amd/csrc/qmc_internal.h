@@ -31,6 +31,12 @@ constexpr int kMaxM = 24;
 constexpr int64_t kMaxPoints = int64_t(1) << 24;  // N = b^m
 constexpr int kMaxLevels = kMaxM + 1;
 constexpr int kMaxSplit = 6;       // at most 64 leaves per subtree
+// The gradient's split level is at most 5: its fused leaf pass keeps one
+// accumulator per lower coordinate and the subtree's leaves in registers, and
+// a 64-leaf subtree needs more than a quarter of a SIMD's registers (three
+// waves per SIMD instead of four; measured slower than moving level 5 onto
+// the matrix cores).
+constexpr int kMaxSplitGrad = 5;
 constexpr int kTileT = 64;         // columns per wave in the leaf kernels
 constexpr int kMaxLowRows = 64;    // rows of A kept in LDS by the leaf kernels
 constexpr int kLdsPadRows = 8;   // zero rows after the leaf kernel's rows of A in LDS

@@ -61,9 +61,9 @@ def adjoint_chain(wl, pts) -> int:
     (<= m levels) and the adjoint level products over K-chunks of <= 1024 rows.
     Gathered tiles: the matrix cores sum at most 4096 points before each FP64
     flush; in base b > 2 the upper coordinates first fold b^{L'} points."""
-    if wl.b == 2 and pts.split_level >= 0:
+    if wl.b == 2 and pts.grad_split_level >= 0:
         return 1024 + wl.m + 64 + 33 + 8
-    L = max(pts.split_level, 0)
+    L = max(pts.grad_split_level, 0)
     return 4096 + wl.b ** L + 16
 
 

@@ -257,12 +257,12 @@ def test_gradient_small(kind, g, h, c):
 def test_gradient_split_bf16_tree(g, h, c):
     """The tree-path adjoint in split BF16 (forward and adjoint upper-level
     products as three BF16 products): every element within the split bound,
-    Frobenius within 1e-5.  w_j = floor(1.5 log2(j+1)) puts four nonempty
-    levels (6 to 9) above the split."""
+    Frobenius within 1e-5.  w_j = floor(1.5 log2(j+1)) puts the nonempty
+    levels 5 to 9 above the gradient's split (5)."""
     wl = small(I.LATTICE, I.RANDOM_SHIFT, m=12, s=90, t=100, g=g, h=h, c=c, K=1.0 if h == I.H_CALL else 0.0,
                R=2, A_scale=0.15, w=I.w_log2_pow(90, 12, 3, 2))
     pts = q.Points.from_workload(wl)
-    assert pts.split_level == 6
+    assert pts.split_level == 6 and pts.grad_split_level == 5
     _check_grad(wl, pts, prec=I.SPLIT_BF16X3, tol=1e-5)
 
 
