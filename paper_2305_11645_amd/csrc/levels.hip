@@ -204,7 +204,8 @@ __global__ __launch_bounds__(256) void levels_gemm(GemmArgs g, const float *__re
 // ------------------------------------------------------------------ forward, packed operands
 // The forward level products with both operands packed once per call into
 // K-step slabs (FP32), or split into (hi, lo) and packed (split BF16):
-//   pack_kernel    the upper-level tables X~_I (per randomisation) and the rows
+//   pack_tables_kernel, pack_a_kernel
+//                  the upper-level tables X~_I (per randomisation) and the rows
 //                  of A of the upper levels, zero-padded to whole tiles and
 //                  K-steps of 16;
 //   gemm_f32p      FP32: v_mfma_f32_16x16x4_f32;
@@ -275,48 +276,85 @@ struct SplitArgs {
 };
 
 // Arrays: [nr][up_pad] of the tables, then [ntn * 256 * kpad] of A, both in
-// slab order; padding (rows past n_I, columns past t, k past tau_I) is 0.
-// One thread writes one run of RUN k-values (16 bytes; in split BF16 16 bytes
-// of hi and of lo).  With tab, blockIdx.y = r packs randomisation r's tables;
-// else the A (grid y = 1).
+// slab order; padding (rows past n_I, columns past t, k past tau_I) is 0.  In
+// split BF16 the hi array is followed (a.half values later) by the lo array.
+
+// The tables: one workgroup per slab (128 rows x 16 k of one level, one
+// randomisation), read in runs of 16 k per row (a wave reads four 64-byte
+// row pieces per load), turned in LDS and written as one contiguous slab.
 template <bool F32>
-__global__ __launch_bounds__(256) void pack_kernel(SplitArgs a, bool tab, const float *__restrict__ tables,
-                                                   const float *__restrict__ A, void *__restrict__ out) {
+__global__ __launch_bounds__(256) void pack_tables_kernel(SplitArgs a, const float *__restrict__ tables,
+                                                          void *__restrict__ out) {
+  constexpr int RUN = F32 ? 4 : 8;
+  __shared__ __attribute__((aligned(16))) float lds[SLAB_A];
+  const Geometry &G = a.G;
+  const int r = blockIdx.y, tid = threadIdx.x;
+  const int64_t q = (int64_t)blockIdx.x * SLAB_A;  // this slab's offset in the randomisation's tables
+  int u = 0;
+  while (u + 1 < G.nup && a.L.tab_off[u + 1] <= q) ++u;
+  const Level &lv = G.lev[G.up[u]];
+  const int ksteps = a.L.taup[u] / SBK;
+  const int64_t sl = (q - a.L.tab_off[u]) / SLAB_A;
+  const int64_t row0 = (sl / ksteps) * SBM;
+  const int k0 = (int)(sl % ksteps) * SBK;
+  const int64_t M = int64_t(1) << lv.nb;
+  const float *src = tables + r * G.table_total + G.lower_total + lv.off;
+#pragma unroll
+  for (int it = 0; it < SLAB_A / 256; ++it) {
+    const int e = it * 256 + tid, ri = e / SBK, k = e % SBK;
+    const int64_t row = row0 + ri;
+    const float x = row < M && k0 + k < lv.tau ? src[row * lv.tau + k0 + k] : 0.f;
+    lds[(k / RUN) * (SBM * RUN) + ri * RUN + k % RUN] = x;
+  }
+  __syncthreads();
+  const int64_t base = (int64_t)r * a.L.up_pad + q;
+  if constexpr (F32) {
+#pragma unroll
+    for (int it = 0; it < SLAB_A / 1024; ++it) {
+      const int o = (it * 256 + tid) * 4;
+      *reinterpret_cast<f32x4v *>(static_cast<float *>(out) + base + o) = *reinterpret_cast<const f32x4v *>(&lds[o]);
+    }
+  } else {
+    static_assert(SLAB_A == 256 * 8, "one run of 8 per thread");
+    const int o = tid * 8;
+    bf16x8v h, l;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const float x = lds[o + i];
+      h[i] = (__bf16)x;
+      l[i] = (__bf16)(x - (float)h[i]);
+    }
+    __bf16 *hi = static_cast<__bf16 *>(out);
+    *reinterpret_cast<bf16x8v *>(hi + base + o) = h;
+    *reinterpret_cast<bf16x8v *>(hi + a.half + base + o) = l;
+  }
+}
+
+// The rows of A: one thread writes one run of RUN k-values of one column
+// (16 bytes; split BF16: 16 bytes of hi and of lo); consecutive threads take
+// consecutive columns, so each row of A is read in whole wave-wide runs.
+template <bool F32>
+__global__ __launch_bounds__(256) void pack_a_kernel(SplitArgs a, const float *__restrict__ A,
+                                                     void *__restrict__ out) {
   constexpr int RUN = F32 ? 4 : 8;
   const Geometry &G = a.G;
-  const int r = blockIdx.y;
-  const int64_t runs = (tab ? a.L.up_pad : (int64_t)a.L.ntn * SBN * a.L.kpad) / RUN;
-  const int64_t base = tab ? (int64_t)r * a.L.up_pad : (int64_t)a.nr * a.L.up_pad;  // the A follows the tables
+  const int64_t runs = (int64_t)a.L.ntn * SBN * a.L.kpad / RUN;
+  const int64_t base = (int64_t)a.nr * a.L.up_pad;  // the A follows the tables
+  const uint32_t ksteps = (uint32_t)(a.L.kpad / SBK);
   for (int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x; c < runs; c += (int64_t)gridDim.x * 256) {
     const int64_t q0 = c * RUN;
+    const uint32_t slab = (uint32_t)(q0 / SLAB_B), in = (uint32_t)(q0 % SLAB_B);
+    const int64_t col = (int64_t)(slab / ksteps) * SBN + (in % (SBN * RUN)) / RUN;
+    const int kk0 = (int)(slab % ksteps) * SBK + (int)(in / (SBN * RUN)) * RUN;
+    int u = 0;
+    while (u + 1 < G.nup && a.L.koff[u + 1] <= kk0) ++u;  // a run lies in one level
+    const Level &lv = G.lev[G.up[u]];
+    const int k0 = kk0 - a.L.koff[u];
+    const bool cok = col < a.t;
+    const float *src = A + (int64_t)(lv.j0 + k0) * a.lda + (cok ? col : 0);
     float x[RUN];
-    if (tab) {
-      int u = 0;
-      while (u + 1 < G.nup && a.L.tab_off[u + 1] <= q0) ++u;
-      const Level &lv = G.lev[G.up[u]];
-      const int64_t q = q0 - a.L.tab_off[u];
-      const uint32_t slab = (uint32_t)(q / SLAB_A), in = (uint32_t)(q % SLAB_A);
-      const uint32_t ksteps = (uint32_t)a.L.taup[u] / SBK;
-      const int64_t row = (int64_t)(slab / ksteps) * SBM + (in % (SBM * RUN)) / RUN;
-      const int k0 = (int)(slab % ksteps) * SBK + (int)(in / (SBM * RUN)) * RUN;
-      const bool rok = row < (int64_t(1) << lv.nb);
-      const float *src = tables + r * G.table_total + G.lower_total + lv.off + (rok ? row : 0) * lv.tau;
 #pragma unroll
-      for (int i = 0; i < RUN; ++i) x[i] = rok && k0 + i < lv.tau ? src[k0 + i] : 0.f;
-    } else {
-      const uint32_t ksteps = (uint32_t)(a.L.kpad / SBK);
-      const uint32_t slab = (uint32_t)(q0 / SLAB_B), in = (uint32_t)(q0 % SLAB_B);
-      const int64_t col = (int64_t)(slab / ksteps) * SBN + (in % (SBN * RUN)) / RUN;
-      const int kk0 = (int)(slab % ksteps) * SBK + (int)(in / (SBN * RUN)) * RUN;
-      int u = 0;
-      while (u + 1 < G.nup && a.L.koff[u + 1] <= kk0) ++u;  // a run lies in one level
-      const Level &lv = G.lev[G.up[u]];
-      const int k0 = kk0 - a.L.koff[u];
-      const bool cok = col < a.t;
-      const float *src = A + (int64_t)(lv.j0 + k0) * a.lda + (cok ? col : 0);
-#pragma unroll
-      for (int i = 0; i < RUN; ++i) x[i] = cok && k0 + i < lv.tau ? src[(int64_t)i * a.lda] : 0.f;
-    }
+    for (int i = 0; i < RUN; ++i) x[i] = cok && k0 + i < lv.tau ? src[(int64_t)i * a.lda] : 0.f;
     if constexpr (F32) {
       f32x4v v;
 #pragma unroll
@@ -555,16 +593,14 @@ static hipError_t launch_levels_packed(const Geometry &G, int prec, const float 
   sa.lda = lda;
   sa.half = packed_values(L, nr);
   const bool f32 = prec == QMC_FP32;
-  const int run = f32 ? 4 : 8;
-  const int64_t truns = L.up_pad / run, aruns = (int64_t)L.ntn * SBN * L.kpad / run;
-  const auto pack = f32 ? pack_kernel<true> : pack_kernel<false>;
-  if (nr > 0 && truns > 0)
-    hipLaunchKernelGGL(pack, dim3((unsigned)std::min<int64_t>(ceil_div(truns, 256), 1024), nr), dim3(256), 0, st,
-                       sa, true, tables, A, buf);
+  const int64_t slabs = L.up_pad / SLAB_A, aruns = (int64_t)L.ntn * SBN * L.kpad / (f32 ? 4 : 8);
+  if (nr > 0 && slabs > 0)
+    hipLaunchKernelGGL(f32 ? pack_tables_kernel<true> : pack_tables_kernel<false>, dim3((unsigned)slabs, nr),
+                       dim3(256), 0, st, sa, tables, buf);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(pack, dim3((unsigned)std::min<int64_t>(ceil_div(aruns, 256), 4096)), dim3(256), 0, st, sa,
-                     false, tables, A, buf);
+  hipLaunchKernelGGL(f32 ? pack_a_kernel<true> : pack_a_kernel<false>,
+                     dim3((unsigned)std::min<int64_t>(ceil_div(aruns, 256), 4096)), dim3(256), 0, st, sa, A, buf);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   SplitGemmArgs g{};
   g.nprob = G.nup;
