@@ -663,7 +663,7 @@ hipError_t launch_levels(const Geometry &G, int prec, const float *tables, int n
 
 // Adjoint partial layout: for each upper level (in order) kchunks blocks of
 // tau_I x ldu floats, per shift.
-int64_t levels_adj_kchunk(int64_t K) { return K < 1024 ? round_up(K, BK) : 1024; }
+int64_t levels_adj_kchunk(int64_t K) { return K < 256 ? round_up(K, BK) : 256; }
 static int adj_chunk(int64_t K) { return (int)levels_adj_kchunk(K); }
 
 int64_t levels_adj_part_floats(const Geometry &G, int t, int64_t ldu) {
@@ -677,9 +677,183 @@ int64_t levels_adj_part_floats(const Geometry &G, int t, int64_t ldu) {
   return n;
 }
 
+// ------------------------------------------------------------------ adjoint, FP32
+// dA_I = X~_I^T S_I on v_mfma_f32_16x16x4_f32: workgroup tiles of TI
+// coordinates x TJ columns over one K-chunk of rows, four waves in a WI x
+// (4 / WI) grid, K-steps of 16 rows staged in LDS with padded row strides (the
+// four rows a wave reads at once fall on distinct banks).  Both operands are
+// row-major in K: X~_I[k][i] (the table) and S_I[k][j].  Levels with at most
+// 32 coordinates take 32 x 256 tiles, at most 64 take 64 x 256, the others
+// 128 x 128, so that a row of S is re-read by few workgroups.
+constexpr int ABK = 16;
+
+struct AdjArgs {
+  int32_t tile0[kMaxGemmProbs];
+  int32_t nprob;
+  int64_t a_rs, b_rs, c_rs, ldb, ldc;
+  struct {
+    int32_t tau, K, kchunk, kchunks, tiles_i, tiles_j;
+    int64_t a_off, b_off, c_off, c_chunk;
+  } p[kMaxLevels];
+};
+
+template <int TI, int TJ, int WI>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void gemm_adj_f32(
+    AdjArgs g, int t, const float *__restrict__ tables, const float *__restrict__ S, float *__restrict__ part) {
+  constexpr int WJ = 4 / WI, BI = TI / (16 * WI), BJ = TJ / (16 * WJ);
+  constexpr int AS = TI + 16, BS = TJ + 16;  // row strides of 16 or 48 (mod 64) floats
+  static_assert(AS % 64 == 16 || AS % 64 == 48, "A rows must fall on distinct banks");
+  static_assert(BS % 64 == 16 || BS % 64 == 48, "B rows must fall on distinct banks");
+  constexpr int NA = ABK * TI / 256, NB4 = ABK * TJ / 1024;  // per thread: X floats, S float4s
+  static_assert(NA >= 1 && NB4 >= 1, "tile too small for the loaders");
+  __shared__ __attribute__((aligned(16))) float As[2][ABK * AS];
+  __shared__ __attribute__((aligned(16))) float Bs[2][ABK * BS];
+  const int r = blockIdx.y;
+  int tile = blockIdx.x, pi = 0;
+#pragma unroll
+  for (int q = 1; q < kMaxGemmProbs; ++q)
+    if (tile >= g.tile0[q]) pi = q;
+  const auto &P = g.p[pi];
+  tile -= g.tile0[pi];
+  // coordinate tiles fastest: neighbouring workgroups share their rows of S
+  const int ti = tile % P.tiles_i;
+  tile /= P.tiles_i;
+  const int tj = tile % P.tiles_j, chunk = tile / P.tiles_j;
+  const int i0 = ti * TI, j0 = tj * TJ;
+  const int kbeg = chunk * P.kchunk, kend = min(P.K, kbeg + P.kchunk);
+  const float *X = tables + r * g.a_rs + P.a_off;
+  const float *Sb = S + r * g.b_rs + P.b_off;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  // loaders: X element tid + 256 q is (row e / TI, coordinate i0 + e % TI);
+  // S float4 tid + 256 q is (row e / (TJ / 4), columns j0 + 4 (e % (TJ / 4)) + 0..3)
+  float ra[NA];
+  f32x4v rb[NB4];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      const int e = tid + 256 * q, k = k0 + e / TI, i = i0 + e % TI;
+      ra[q] = k < kend && i < P.tau ? X[(int64_t)k * P.tau + i] : 0.f;
+    }
+#pragma unroll
+    for (int q = 0; q < NB4; ++q) {
+      const int e = tid + 256 * q, k = k0 + e / (TJ / 4), j = j0 + 4 * (e % (TJ / 4));
+      // columns past t (up to ldb) only reach outputs that are not stored
+      rb[q] = k < kend && j < g.ldb ? *reinterpret_cast<const f32x4v *>(&Sb[(int64_t)k * g.ldb + j])
+                                    : f32x4v{0.f, 0.f, 0.f, 0.f};
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      const int e = tid + 256 * q;
+      As[buf][(e / TI) * AS + e % TI] = ra[q];
+    }
+#pragma unroll
+    for (int q = 0; q < NB4; ++q) {
+      const int e = tid + 256 * q;
+      *reinterpret_cast<f32x4v *>(&Bs[buf][(e / (TJ / 4)) * BS + 4 * (e % (TJ / 4))]) = rb[q];
+    }
+  };
+  f32x4v acc[BI][BJ];
+#pragma unroll
+  for (int i = 0; i < BI; ++i)
+#pragma unroll
+    for (int j = 0; j < BJ; ++j) acc[i][j] = f32x4v{0.f, 0.f, 0.f, 0.f};
+  load(kbeg);
+  store(0);
+  __syncthreads();
+  int cur = 0;
+  const int wi = (w / WJ) * (16 * BI), wj = (w % WJ) * (16 * BJ), kl = lane >> 4, cl = lane & 15;
+  for (int k0 = kbeg; k0 < kend; k0 += ABK) {
+    const bool more = k0 + ABK < kend;
+    if (more) load(k0 + ABK);
+#pragma unroll
+    for (int c = 0; c < ABK / 4; ++c) {
+      const int kr = 4 * c + kl;  // this lane's row of the 4-row step
+      float xa[BI], xb[BJ];
+#pragma unroll
+      for (int i = 0; i < BI; ++i) xa[i] = As[cur][kr * AS + wi + 16 * i + cl];
+#pragma unroll
+      for (int j = 0; j < BJ; ++j) xb[j] = Bs[cur][kr * BS + wj + 16 * j + cl];
+#pragma unroll
+      for (int i = 0; i < BI; ++i)
+#pragma unroll
+        for (int j = 0; j < BJ; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[i], xb[j], acc[i][j], 0, 0, 0);
+    }
+    if (more) store(cur ^ 1);
+    __syncthreads();
+    cur ^= 1;
+  }
+  // D of a 16 x 16 block: acc[v] at row 4 (lane / 16) + v, column lane % 16
+  float *C = part + r * g.c_rs + P.c_off + (int64_t)chunk * P.c_chunk;
+#pragma unroll
+  for (int i = 0; i < BI; ++i)
+#pragma unroll
+    for (int j = 0; j < BJ; ++j) {
+      const int col = j0 + wj + 16 * j + cl;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = i0 + wi + 16 * i + 4 * kl + v;
+        if (row < P.tau && col < t) C[(int64_t)row * g.ldc + col] = acc[i][j][v];
+      }
+    }
+}
+
 hipError_t launch_levels_adj(const Geometry &G, int prec, const float *tables, int nr,
                              const float *S, int t, int64_t ldu, float *part, hipStream_t st) {
   LaunchTimer tm("levels_adj", st);
+  if (prec == QMC_FP32) {
+    if (G.nup == 0 || nr == 0) return hipSuccess;
+    if (ldu % 4 != 0) return hipErrorInvalidValue;
+    // three launches: levels with tau <= 32 on 32 x 256 tiles, tau <= 64 on
+    // 64 x 256, the others on 128 x 128
+    for (int shape = 0; shape < 3; ++shape) {
+      const int TI = shape == 0 ? 32 : shape == 1 ? 64 : 128, TJ = shape == 2 ? 128 : 256;
+      AdjArgs a{};
+      a.a_rs = G.table_total;
+      a.b_rs = (2 * G.nsub) * ldu;  // S pyramid rows per shift
+      a.c_rs = levels_adj_part_floats(G, t, ldu);
+      a.ldb = ldu;
+      a.ldc = ldu;
+      int tiles = 0;
+      int64_t poff = 0, soff = 0;
+      int Iprev = G.split;
+      for (int u = 0; u < G.nup; ++u) {
+        const Level &L = G.lev[G.up[u]];
+        for (int I = Iprev; I < G.up[u]; ++I) soff += int64_t(1) << (G.m - I);  // S_I follows levels split .. I-1
+        Iprev = G.up[u];
+        const int K = 1 << L.nb, kchunk = adj_chunk(K), kchunks = (int)ceil_div(K, kchunk);
+        const int64_t c_off = poff;
+        poff += (int64_t)kchunks * L.tau * ldu;
+        if ((L.tau <= 32 ? 0 : L.tau <= 64 ? 1 : 2) != shape) continue;
+        auto &P = a.p[a.nprob];
+        P.tau = L.tau;
+        P.K = K;
+        P.kchunk = kchunk;
+        P.kchunks = kchunks;
+        P.tiles_i = (int)ceil_div(P.tau, TI);
+        P.tiles_j = (int)ceil_div(t, TJ);
+        P.a_off = G.lower_total + L.off;
+        P.b_off = soff * ldu;
+        P.c_off = c_off;
+        P.c_chunk = (int64_t)L.tau * ldu;
+        a.tile0[a.nprob++] = tiles;
+        tiles += P.tiles_i * P.tiles_j * P.kchunks;
+      }
+      if (tiles == 0) continue;
+      for (int q = a.nprob; q < kMaxGemmProbs; ++q) a.tile0[q] = 0x7fffffff;
+      if (shape == 2)
+        hipLaunchKernelGGL((gemm_adj_f32<128, 128, 2>), dim3(tiles, nr), dim3(256), 0, st, a, t, tables, S, part);
+      else if (shape == 1)
+        hipLaunchKernelGGL((gemm_adj_f32<64, 256, 1>), dim3(tiles, nr), dim3(256), 0, st, a, t, tables, S, part);
+      else
+        hipLaunchKernelGGL((gemm_adj_f32<32, 256, 1>), dim3(tiles, nr), dim3(256), 0, st, a, t, tables, S, part);
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
   GemmArgs a = {};
   a.oscale = 1.0f;
   a.a_rs = G.table_total;
