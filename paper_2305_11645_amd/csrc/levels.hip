@@ -27,6 +27,8 @@
 //   32x32x16 bf16: A: lane l holds A[l%32][8(l/32) + 0..7]; B: B[8(l/32)+0..7][l%32];
 //                 D as for 32x32x2.
 #include <algorithm>
+#include <cstdlib>
+#include <cstring>
 
 #include "qmc_internal.h"
 
@@ -653,10 +655,66 @@ static hipError_t run_gemm(const GemmArgs &a, int prec, int nr, const float *A, 
   return hipGetLastError();
 }
 
+// The forward products straight from the tables and A on 64 x 64 tiles (no
+// packing pass): for grids too small to fill the chip with 128 x 256 tiles.
+static hipError_t launch_levels_direct(const Geometry &G, int prec, const float *tables, int nr, const float *A,
+                                       int t, int64_t lda, float *U, int64_t ldu, float oscale, hipStream_t st) {
+  GemmArgs a = {};
+  a.oscale = oscale;
+  a.a_rs = G.table_total;
+  a.b_rs = 0;
+  a.c_rs = G.urows * ldu;
+  a.ldb = lda;
+  a.ldc = ldu;
+  int tiles = 0;
+  for (int u = 0; u < G.nup; ++u) {
+    const Level &L = G.lev[G.up[u]];
+    GemmProb &P = a.p[a.nprob++];
+    P.M = 1 << L.nb;
+    P.N = t;
+    P.K = L.tau;
+    P.tiles_m = (int)ceil_div(P.M, BM);
+    P.tiles_n = (int)ceil_div(t, BN);
+    P.kchunk = (int)round_up(P.K, BK);
+    P.kchunks = 1;
+    P.tile0 = tiles;
+    P.a_off = G.lower_total + L.off;
+    P.a_si = L.tau;
+    P.a_sk = 1;
+    P.b_off = (int64_t)L.j0 * lda;
+    P.c_off = L.uoff * ldu;
+    P.c_chunk = 0;
+    tiles += P.tiles_m * P.tiles_n;
+  }
+  a.total_tiles = tiles;
+  finish_tile_table(a);
+  return run_gemm<false>(a, prec, nr, tables, A, U, st);
+}
+
+// Packed 128 x 256 tiles are taken when there are enough of them to fill the
+// chip (all randomisations), or half as many when no level has more than 512
+// coordinates (the longest tiles, dispatched first, then end in time);
+// otherwise the 64 x 64 direct form, with eight times as many tiles and no
+// packing pass (measured: C2, C4's stored-Y product, C5).
+constexpr int64_t kMinPackedTiles = 1536;
+
 hipError_t launch_levels(const Geometry &G, int prec, const float *tables, int nr, const float *A,
                          int t, int64_t lda, float *U, int64_t ldu, float oscale, void *pack, hipStream_t st) {
   LaunchTimer tm("levels", st);
   if (G.nup == 0 || nr == 0) return hipSuccess;
+  const SplitLayout L = split_layout(G, t);
+  int64_t tiles = 0;
+  int kmax = 0;
+  for (int u = 0; u < G.nup; ++u) {
+    tiles += (int64_t)L.tiles_m[u] * L.ntn;
+    kmax = std::max(kmax, L.taup[u]);
+  }
+  bool direct = tiles * nr < (kmax <= 512 ? kMinPackedTiles / 2 : kMinPackedTiles);
+  if (const char *env = getenv("QMC_LEVELS_FORM")) {  // test and measurement switch: "direct" or "packed"
+    if (!strcmp(env, "direct")) direct = true;
+    if (!strcmp(env, "packed")) direct = false;
+  }
+  if (direct) return launch_levels_direct(G, prec, tables, nr, A, t, lda, U, ldu, oscale, st);
   if (!pack || ldu % 4 != 0) return hipErrorInvalidValue;
   return launch_levels_packed(G, prec, tables, nr, A, t, lda, U, ldu, oscale, pack, st);
 }

@@ -88,10 +88,14 @@ def _check_Y(wl, Y, r, prec):
 @pytest.mark.parametrize("kind", KINDS)
 @pytest.mark.parametrize("rand", RANDS)
 @pytest.mark.parametrize("prec", [I.FP32, I.SPLIT_BF16X3])
-def test_matvec_elementwise(kind, rand, prec):
+@pytest.mark.parametrize("form", ["direct", "packed"])
+def test_matvec_elementwise(kind, rand, prec, form, monkeypatch):
     """Y = X A for every element within the FP32 (or split-bf16) error bound.
     t = 100 spans two 64-column tiles with a ragged tail; m = 9 gives several
-    subtrees and several upper levels."""
+    subtrees and several upper levels.  Both forms of the upper-level products:
+    straight from the tables on 64 x 64 tiles, and from the packed K-step slabs
+    on 128 x 256 tiles (a small grid takes the first unless forced)."""
+    monkeypatch.setenv("QMC_LEVELS_FORM", form)
     torch = torch_cuda()
     mp = I.MAP_INVNORM if rand == I.DIGITAL_SHIFT else I.MAP_ID
     wl = small(kind, rand, mp)
@@ -153,9 +157,12 @@ def test_matvec_strided_A_and_Y():
 @pytest.mark.parametrize("kind", KINDS)
 @pytest.mark.parametrize("g,h,c", [(I.G_COS, I.H_ID, 1.0), (I.G_EXP, I.H_ID, -0.7),
                                    (I.G_EXP, I.H_CALL, 0.2), (I.G_ID, I.H_ID, 1.0)])
-def test_estimate_small(kind, g, h, c):
-    """Q[r] against the oracle to 1e-6 relative for every integrand family."""
+@pytest.mark.parametrize("form", ["direct", "packed"])
+def test_estimate_small(kind, g, h, c, form, monkeypatch):
+    """Q[r] against the oracle to 1e-6 relative for every integrand family,
+    with either form of the upper-level products."""
     from oracle import oracle as O
+    monkeypatch.setenv("QMC_LEVELS_FORM", form)
     torch = torch_cuda()
     rand = I.DIGITAL_SHIFT if kind == I.DIGITAL_NET else I.RANDOM_SHIFT
     K = 1.0 if h == I.H_CALL else 0.0
