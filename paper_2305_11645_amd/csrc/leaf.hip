@@ -288,7 +288,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
   const int first = bx * a.sub_per + min(bx, a.sub_rem);
   const int last = first + a.sub_per + (bx < a.sub_rem ? 1 : 0);
   // subtree root: the upper levels' rows, requested RB at a time
-  constexpr int RB = MODE == kModeSum || MODE == kModeStoreY ? kRootBatch : 1;
+  constexpr int RB = MODE == kModeGrad ? 1 : kRootBatch;
   auto root_batch = [&](int rho, int u0, float (&rv)[RB][CPL]) {
 #pragma unroll
     for (int i = 0; i < RB; ++i) {  // entries past nup are zero: they read row 0
@@ -367,29 +367,32 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
 #pragma unroll
       for (int q = 0; q < CPL; ++q)
         if (live[q]) acc += (double)s[q];
-    } else if constexpr (MODE == kModeStoreY) {
-      // the lean descent of the summing mode, then the 64 rows of Y
+    } else if constexpr (MODE == kModeStoreY || MODE == kModePoint) {
+      // the lean descent of the summing mode, then the 64 rows of Y, or the
+      // leaves' g summed over the wave's columns (one sum per point)
       uint64_t taus = a.taus;
       asm volatile("" : "+s"(taus));
       int xo = 0, j0 = jlow;
       float y[1][NL];
       y[0][0] = root[0];
       descend_lean<LP, LP - 1, 0, 1>(y, rec, xo, j0, taus, Alds + lcol);
-      if (a.nup > 0 && rho + a.nw < last) root_batch(rho + a.nw, 0, rvn);
+      if constexpr (MODE == kModeStoreY) {
+        if (a.nup > 0 && rho + a.nw < last) root_batch(rho + a.nw, 0, rvn);
 #pragma unroll
-      for (int c = 0; c < NL; ++c) Y[((int64_t)rho + (int64_t)c * a.nsub) * a.ldy + ct * CW + lcol] = y[0][c];
+        for (int c = 0; c < NL; ++c) Y[((int64_t)rho + (int64_t)c * a.nsub) * a.ldy + ct * CW + lcol] = y[0][c];
+      } else {
+        float v[64];
+#pragma unroll
+        for (int c = 0; c < 64; ++c) v[c] = (c < NL && live[0]) ? g_val<GF>(y[0][c < NL ? c : 0]) : 0.f;
+        transpose_step<32>(v, lane);
+        if (lane < NL) ppart[(((int64_t)rl * a.tct + ct) * a.nsub + rho) * NL + lane] = v[0];
+      }
     } else {
       float y[NL];
       y[0] = root[0];
       const bool live0 = live[0];
       descend_to<LP, LP - 1, 0>(y, rec, a.lv, Alds, kTileT, lane);
-      if (MODE == kModePoint) {
-        float v[64];
-#pragma unroll
-        for (int c = 0; c < 64; ++c) v[c] = (c < NL && live0) ? g_val<GF>(y[c < NL ? c : 0]) : 0.f;
-        transpose_step<32>(v, lane);
-        if (lane < NL) ppart[(((int64_t)rl * a.tct + ct) * a.nsub + rho) * NL + lane] = v[0];
-      } else {  // kModeGrad
+      {  // kModeGrad
         float S[NL];
         float s = 0.f;
         const float *hk = hd ? hd + ((int64_t)rl * a.nsub + rho) * NL : nullptr;
