@@ -861,7 +861,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
 hipError_t launch_levels_adj(const Geometry &G, int prec, const float *tables, int nr,
                              const float *S, int t, int64_t ldu, float *part, hipStream_t st) {
   LaunchTimer tm("levels_adj", st);
-  if (prec == QMC_FP32) {
+  // below about 2 GFLOP the three launches of the tiled form cost more than
+  // the products; the one-launch 64 x 64 form then takes them (C2's gradient)
+  double flops = 0.0;
+  for (int u = 0; u < G.nup; ++u) {
+    const Level &L = G.lev[G.up[u]];
+    flops += 2.0 * L.tau * (double)(int64_t(1) << L.nb) * t * nr;
+  }
+  bool tiled = flops >= 2e9;
+  if (const char *env = getenv("QMC_LEVELS_FORM")) {  // test and measurement switch, as for the forward form
+    if (!strcmp(env, "direct")) tiled = false;
+    if (!strcmp(env, "packed")) tiled = true;
+  }
+  if (prec == QMC_FP32 && tiled) {
     if (G.nup == 0 || nr == 0) return hipSuccess;
     if (ldu % 4 != 0) return hipErrorInvalidValue;
     // three launches: levels with tau <= 32 on 32 x 256 tiles, tau <= 64 on

@@ -249,14 +249,31 @@ def test_workspace_allocation_failure_leaves_the_point_set_usable(monkeypatch):
 
 @pytest.mark.parametrize("kind", KINDS)
 @pytest.mark.parametrize("g,h,c", [(I.G_COS, I.H_ID, 1.0), (I.G_EXP, I.H_CALL, 0.2)])
-def test_gradient_small(kind, g, h, c):
+@pytest.mark.parametrize("form", ["direct", "packed"])
+def test_gradient_small(kind, g, h, c, form, monkeypatch):
     """dQ/dA against the oracle gradient: every element within its FP32 error
     bound (c u |X|^T|G| plus the propagated error of y, see gpu_common), and
-    relative Frobenius <= 1e-6 per shift."""
+    relative Frobenius <= 1e-6 per shift.  Both forms of the level products
+    (the 64 x 64 ones, and the packed forward and tiled adjoint ones that large
+    problems take)."""
+    monkeypatch.setenv("QMC_LEVELS_FORM", form)
     wl = small(kind, I.DIGITAL_SHIFT if kind == I.DIGITAL_NET else I.RANDOM_SHIFT, m=10, s=50, t=80, g=g, h=h,
                c=c, K=1.0 if h == I.H_CALL else 0.0, R=2)
     pts = q.Points.from_workload(wl)
     assert pts.split_level >= 0
+    _check_grad(wl, pts)
+
+
+@pytest.mark.parametrize("form", ["direct", "packed"])
+def test_gradient_all_adjoint_tile_shapes(form, monkeypatch):
+    """Upper levels with 32, 64, 128 and 45 coordinates (w_j = floor(log2(j+1)),
+    s = 300) take all three tile shapes of the tiled adjoint products; every
+    element of dA within its FP32 bound, in both forms."""
+    monkeypatch.setenv("QMC_LEVELS_FORM", form)
+    wl = small(I.LATTICE, I.RANDOM_SHIFT, m=12, s=300, t=100, g=I.G_COS, h=I.H_ID, c=1.0, R=1, A_scale=0.1,
+               w=I.w_log2(300, 12))
+    pts = q.Points.from_workload(wl)
+    assert pts.grad_split_level == 5
     _check_grad(wl, pts)
 
 
