@@ -58,7 +58,8 @@ def adjoint_chain(wl, pts) -> int:
     Tree path (base 2, periodic): inside a subtree at most 2^{L'} <= 64 leaf
     terms per level product and L' folds, the per-wave accumulator over at
     most 33 subtrees, the waves of a workgroup; above L' the fold pyramid
-    (<= m levels) and the adjoint level products over K-chunks of <= 1024 rows.
+    (<= m levels) and the adjoint level products over K-chunks of <= 256 rows
+    (the bound allows 1024).
     Gathered tiles: the matrix cores sum at most 4096 points before each FP64
     flush; in base b > 2 the upper coordinates first fold b^{L'} points."""
     if wl.b == 2 and pts.grad_split_level >= 0:
