@@ -334,10 +334,13 @@ def test_iid_tables_bit_exact(mp):
 
 
 @pytest.mark.parametrize("prec", [I.FP32, I.SPLIT_BF16X3])
-def test_iid_matvec_elementwise(prec):
-    """Reduced Monte Carlo products Y = X A, every element within the bound."""
+@pytest.mark.parametrize("m,mp", [(9, I.MAP_INVNORM), (12, I.MAP_INVNORM), (12, I.MAP_CENTER)])
+def test_iid_matvec_elementwise(prec, m, mp):
+    """Reduced Monte Carlo products Y = X A, every element within the bound.
+    m = 12 puts all 40 coordinates below the split (no upper level) over 64
+    subtree roots."""
     torch = torch_cuda()
-    wl = iid_small(I.MAP_INVNORM, A_scale=0.1)
+    wl = iid_small(mp, m=m, A_scale=0.1, w=I.w_log2(40, m + 1))
     pts = q.Points.from_workload(wl)
     A = to_dev(wl.A, torch)
     for r in range(wl.R):
