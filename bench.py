@@ -493,10 +493,19 @@ def bench_estimate(args, wl) -> int:
         mf = 2.0 * wl.N * jlow * wl.t * wl.R * (3 if prec == I.SPLIT_BF16X3 else 1)
         peak = MFMA_PEAK_TFLOPS[prec]
         achieved = mf / (leaf_ms * 1e-3) / 1e12
+        # the method's own count (Section 3, the remark after Algorithm 4):
+        # N jlow t R additions and t R sum_j n_j multiplications, one flop each
+        nsum = float(np.sum(wl.b ** (wl.m - np.minimum(wl.w, wl.m))[: jlow]))
+        method = float(wl.N * jlow * wl.t * wl.R + wl.t * wl.R * nsum)
         roofline = {"bound": "mfma", "kernel": "alg4_kernel", "achieved": round(achieved, 3),
                     "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
                     "traffic": leaf_traffic(args.config, kernel="alg4_kernel"), "avg_ms": round(leaf_ms, 5),
-                    "algorithmic_flops": mf, "measured_rates_TFLOP_per_s": measured_mfma()}
+                    "algorithmic_flops": mf,
+                    "note": "algorithmic_flops are the matrix-core multiply-adds the kernel issues "
+                            "(each of the method's additions becomes one multiply-add on a point value)",
+                    "method_flops": method,
+                    "frac_method_count": round(method / (leaf_ms * 1e-3) / 1e12 / MFMA_PEAK_TFLOPS[0], 4),
+                    "measured_rates_TFLOP_per_s": measured_mfma()}
     else:
         slots = leaf_algorithmic_slots(wl, pts.split_level)
         achieved = 2 * slots / (leaf_ms * 1e-3) / 1e12
