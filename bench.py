@@ -369,8 +369,9 @@ def main() -> int:
                          "grad: Q and dQ/dA")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the sharding plan is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path (it would shard "
+              "by randomisation, subtree root or column tile, with one all-reduce per call)",
+              file=sys.stderr)
         return 2
 
     import torch
