@@ -176,7 +176,7 @@ enum Op { kOpMatvec = 0, kOpEstimate = 1, kOpGrad = 2 };
 
 struct Work {
   float *tables, *U, *ppart, *S, *dlow, *dup, *hd, *root;
-  void *bsplit;  // the packed operands of the upper-level products
+  void *pack;  // the packed operands of the upper-level products
   float *Gm;  // gather path, gradient: the sensitivities G, [nr][N][t]
   double *partial, *ppartial;
   double *glow, *gup;  // gather path, gradient: FP64 chunk partials of dA
@@ -213,7 +213,7 @@ size_t carve(const qmc::Geometry &G, int op, int t, const qmc_integrand *f, int 
   }
   wk.tables = c.take<float>((size_t)nr * G.table_total + kTablePad);
   wk.U = c.take<float>((size_t)nr * G.urows * ldu);
-  if (G.nup > 0) wk.bsplit = c.take<char>((size_t)levels_split_bytes(G, nr, t));
+  if (G.nup > 0) wk.pack = c.take<char>((size_t)levels_pack_bytes(G, nr, t));
   if (op == kOpMatvec) return c.used;
   const bool sep = f->h == QMC_H_ID;
   wk.partial = c.take<double>((size_t)nr * std::max(lp.gx * lp.gy, lg.gx * lg.gy));
@@ -810,7 +810,7 @@ qmc_status qmc_reduced_matvec(qmc_points p, int32_t r, const float *A, int32_t t
     return QMC_OK;
   }
   QMC_HIP(launch_tables(G, p->D, r, 1, wk.tables, nullptr, 0, st), "tables launch");
-  QMC_HIP(launch_levels(G, prec, wk.tables, 1, A, t, lda, wk.U, ldu, 1.0f, wk.bsplit, st), "levels launch");
+  QMC_HIP(launch_levels(G, prec, wk.tables, 1, A, t, lda, wk.U, ldu, 1.0f, wk.pack, st), "levels launch");
   LeafOut o{};
   o.Y = Y;
   o.ldy = ldy;
@@ -873,7 +873,7 @@ static qmc_status estimate_impl(qmc_points p, const float *A, int32_t t, int64_t
 
   QMC_HIP(launch_tables(G, p->D, 0, nr, wk.tables, nullptr, 0, st), "tables launch");
   const int leaf_mode = !sep ? kModePoint : (grad ? kModeGrad : kModeSum);
-  QMC_HIP(launch_levels(G, prec, wk.tables, nr, A, t, lda, wk.U, ldu, g_scale(*f, leaf_mode), wk.bsplit, st),
+  QMC_HIP(launch_levels(G, prec, wk.tables, nr, A, t, lda, wk.U, ldu, g_scale(*f, leaf_mode), wk.pack, st),
           "levels launch");
   LeafOut o{};
   if (sep) {

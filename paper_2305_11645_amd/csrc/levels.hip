@@ -231,7 +231,7 @@ typedef float f32x4v __attribute__((ext_vector_type(4)));
 constexpr int SBM = 128, SBN = 256, SBK = 16;
 constexpr int SLAB_A = SBM * SBK, SLAB_B = SBN * SBK;  // values per slab
 
-struct SplitLayout {
+struct PackLayout {
   int64_t up_pad;                  // values of one randomisation's packed upper tables
   int64_t kpad;                    // padded upper coordinates (K-steps of 16) of the packed A
   int32_t ntn;                     // column tiles of 256
@@ -241,8 +241,8 @@ struct SplitLayout {
   int32_t tiles_m[kMaxLevels];     // per upper level u: row tiles of 128
 };
 
-static SplitLayout split_layout(const Geometry &G, int t) {
-  SplitLayout L{};
+static PackLayout pack_layout(const Geometry &G, int t) {
+  PackLayout L{};
   int64_t off = 0;
   int32_t k = 0;
   for (int u = 0; u < G.nup; ++u) {
@@ -261,17 +261,17 @@ static SplitLayout split_layout(const Geometry &G, int t) {
 }
 
 // values of the packed tables of nr randomisations plus the packed A
-static int64_t packed_values(const SplitLayout &L, int nr) {
+static int64_t packed_values(const PackLayout &L, int nr) {
   return (int64_t)nr * L.up_pad + (int64_t)L.ntn * SBN * L.kpad;
 }
 
-int64_t levels_split_bytes(const Geometry &G, int nr, int t) {
-  return 4 * packed_values(split_layout(G, t), nr);  // FP32, or bf16 hi and lo
+int64_t levels_pack_bytes(const Geometry &G, int nr, int t) {
+  return 4 * packed_values(pack_layout(G, t), nr);  // FP32, or bf16 hi and lo
 }
 
-struct SplitArgs {
+struct PackArgs {
   Geometry G;
-  SplitLayout L;
+  PackLayout L;
   int32_t nr, t;
   int64_t lda;
   int64_t half;  // split BF16: values per hi / lo array
@@ -285,7 +285,7 @@ struct SplitArgs {
 // randomisation), read in runs of 16 k per row (a wave reads four 64-byte
 // row pieces per load), turned in LDS and written as one contiguous slab.
 template <bool F32>
-__global__ __launch_bounds__(256) void pack_tables_kernel(SplitArgs a, const float *__restrict__ tables,
+__global__ __launch_bounds__(256) void pack_tables_kernel(PackArgs a, const float *__restrict__ tables,
                                                           void *__restrict__ out) {
   constexpr int RUN = F32 ? 4 : 8;
   __shared__ __attribute__((aligned(16))) float lds[SLAB_A];
@@ -336,7 +336,7 @@ __global__ __launch_bounds__(256) void pack_tables_kernel(SplitArgs a, const flo
 // (16 bytes; split BF16: 16 bytes of hi and of lo); consecutive threads take
 // consecutive columns, so each row of A is read in whole wave-wide runs.
 template <bool F32>
-__global__ __launch_bounds__(256) void pack_a_kernel(SplitArgs a, const float *__restrict__ A,
+__global__ __launch_bounds__(256) void pack_a_kernel(PackArgs a, const float *__restrict__ A,
                                                      void *__restrict__ out) {
   constexpr int RUN = F32 ? 4 : 8;
   const Geometry &G = a.G;
@@ -376,7 +376,7 @@ __global__ __launch_bounds__(256) void pack_a_kernel(SplitArgs a, const float *_
   }
 }
 
-struct SplitGemmArgs {
+struct PackGemmArgs {
   int32_t tile0[kMaxGemmProbs];
   int32_t nprob;
   float oscale;
@@ -391,7 +391,7 @@ struct SplitGemmArgs {
 struct TileRef {
   int pi, tm, tn;
 };
-__device__ __forceinline__ TileRef tile_of(const SplitGemmArgs &g) {
+__device__ __forceinline__ TileRef tile_of(const PackGemmArgs &g) {
   int tile = blockIdx.x, pi = 0;
 #pragma unroll
   for (int q = 1; q < kMaxGemmProbs; ++q)
@@ -418,7 +418,7 @@ __device__ __forceinline__ void store_rows(const float *E, float *C, int64_t ldc
 constexpr int ES32 = 132, ES16 = 136;  // epilogue row strides: the 16-row groups' writes on distinct banks
 
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void gemm_f32p(
-    SplitGemmArgs g, const float *__restrict__ Ap, const float *__restrict__ Bp, float *__restrict__ Cbase) {
+    PackGemmArgs g, const float *__restrict__ Ap, const float *__restrict__ Bp, float *__restrict__ Cbase) {
   __shared__ __attribute__((aligned(16))) float Ls[2 * (SLAB_A + SLAB_B)];  // [buffer][A slab, B slab]
   static_assert(4 * 16 * ES32 <= 2 * (SLAB_A + SLAB_B), "epilogue does not fit");
   const int r = blockIdx.y;
@@ -492,7 +492,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
 }
 
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void gemm_bf16x3(
-    SplitGemmArgs g, const __bf16 *__restrict__ Ahi, const __bf16 *__restrict__ Alo,
+    PackGemmArgs g, const __bf16 *__restrict__ Ahi, const __bf16 *__restrict__ Alo,
     const __bf16 *__restrict__ Bhi, const __bf16 *__restrict__ Blo, float *__restrict__ Cbase) {
   __shared__ __attribute__((aligned(16))) __bf16 Ls[2 * 2 * (SLAB_A + SLAB_B)];  // [buffer][hi, lo][A, B slab]
   static_assert(4 * 16 * ES16 * 4 <= 2 * 2 * (SLAB_A + SLAB_B) * 2, "epilogue does not fit");
@@ -585,9 +585,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
 static hipError_t launch_levels_packed(const Geometry &G, int prec, const float *tables, int nr, const float *A,
                                        int t, int64_t lda, float *U, int64_t ldu, float oscale, void *buf,
                                        hipStream_t st) {
-  const SplitLayout L = split_layout(G, t);
+  const PackLayout L = pack_layout(G, t);
   const int64_t ntab = (int64_t)nr * L.up_pad;
-  SplitArgs sa;
+  PackArgs sa;
   sa.G = G;
   sa.L = L;
   sa.nr = nr;
@@ -604,7 +604,7 @@ static hipError_t launch_levels_packed(const Geometry &G, int prec, const float 
   hipLaunchKernelGGL(f32 ? pack_a_kernel<true> : pack_a_kernel<false>,
                      dim3((unsigned)std::min<int64_t>(ceil_div(aruns, 256), 4096)), dim3(256), 0, st, sa, A, buf);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  SplitGemmArgs g{};
+  PackGemmArgs g{};
   g.nprob = G.nup;
   g.oscale = oscale;
   g.a_rs = L.up_pad;
@@ -702,7 +702,7 @@ hipError_t launch_levels(const Geometry &G, int prec, const float *tables, int n
                          int t, int64_t lda, float *U, int64_t ldu, float oscale, void *pack, hipStream_t st) {
   LaunchTimer tm("levels", st);
   if (G.nup == 0 || nr == 0) return hipSuccess;
-  const SplitLayout L = split_layout(G, t);
+  const PackLayout L = pack_layout(G, t);
   int64_t tiles = 0;
   int kmax = 0;
   for (int u = 0; u < G.nup; ++u) {

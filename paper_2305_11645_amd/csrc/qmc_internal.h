@@ -171,12 +171,12 @@ hipError_t launch_point_matrix(const Geometry &G, const DevSpec &D, int r, float
                                hipStream_t st);
 
 // Grouped upper-level products U_I = oscale X~_I A_I for shifts [0, nr) of the table buffer.
-// pack (levels_split_bytes(G, nr, t) bytes, 16-byte aligned) receives the
+// pack (levels_pack_bytes(G, nr, t) bytes, 16-byte aligned) receives the
 // operands packed into K-step slabs (split BF16: split into hi and lo) once,
 // then multiplied; ldu is a multiple of 4.
 hipError_t launch_levels(const Geometry &G, int prec, const float *tables, int nr, const float *A,
                          int t, int64_t lda, float *U, int64_t ldu, float oscale, void *pack, hipStream_t st);
-int64_t levels_split_bytes(const Geometry &G, int nr, int t);
+int64_t levels_pack_bytes(const Geometry &G, int nr, int t);
 
 // Adjoint of the upper levels: dA_I = X~_I^T S_I; S pyramid rows as in fold.
 hipError_t launch_levels_adj(const Geometry &G, int prec, const float *tables, int nr,
