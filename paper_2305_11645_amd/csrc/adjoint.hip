@@ -14,7 +14,9 @@ namespace qmc {
 // of them, indexed at compile time by level and position in the level), so
 // the transposed recursion needs no LDS traffic per subtree, and a workgroup
 // only stages its rows of A: four waves per workgroup and, with L' <= 5 (at
-// most 31 accumulators and 32 leaves per lane), five per SIMD.
+// most 31 accumulators and 32 leaves per lane), six waves per SIMD for cos and
+// y (80 registers, 12 bytes spilled for cos: measured faster than five) and
+// five for exp, whose leaf block holds more values (six would spill 36 bytes).
 // Per subtree: the forward descent of the summing mode to the level-1 nodes,
 // then level 0 fused with the integrand (leaves c and c + 2^{L'-1} of node c:
 // their sensitivities G'_k, the level-0 product, and their sum as the node's
@@ -124,7 +126,7 @@ __device__ __forceinline__ void leaf_grad_block(float (&y)[1 << LP], const float
 }
 
 template <int LP, int GF, bool HD>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void grad_kernel(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GF == QMC_G_EXP ? 5 : 6))) void grad_kernel(
     LeafArgs a, const float *__restrict__ tables, const float *__restrict__ U, const float *__restrict__ A,
     double *__restrict__ partial, float *__restrict__ dApart, float *__restrict__ Sroot,
     const float *__restrict__ hd) {
