@@ -221,7 +221,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   // every wave of the workgroup works on column tile ct (CW columns), on its
   // own subtrees; lane column q is ct CW + q 64 + lane
-  const int bx = blockIdx.x, ct = blockIdx.y, rl = blockIdx.z;
+  // Storing mode: workgroups are taken column tile first, so the tiles of one
+  // subtree group run together and their stores fill whole rows of Y at once.
+  const int lin = (int)(blockIdx.x + blockIdx.y * gridDim.x);
+  const int bx = MODE == kModeStoreY ? lin / (int)gridDim.y : (int)blockIdx.x;
+  const int ct = MODE == kModeStoreY ? lin % (int)gridDim.y : (int)blockIdx.y;
+  const int rl = blockIdx.z;
   const int col = ct * CW + lane;
   // Storing mode: a lane past column t does the last column's work and stores
   // the same values to the same addresses, so the stores need no branch (a
@@ -258,6 +263,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
     }
   }
   float *dAl = smem + (jlow + kLdsPadRows) * CW + w * jlow * kTileT;
+  // Storing mode: a record of at most kRecLds floats is copied to the wave's
+  // own LDS slot with one round of vector loads, and the descent reads its
+  // point values there instead of in one scalar round trip per batch.
+  float *recl = smem + (jlow + kLdsPadRows) * CW + w * kRecSlot;
+  const bool rec_lds = MODE == kModeStoreY && a.rec <= kRecLds;
   if (MODE == kModeGrad)
     for (int e = lane; e < jlow * kTileT; e += 64) dAl[e] = 0.f;
   __syncthreads();
@@ -375,7 +385,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
       int xo = 0, j0 = jlow;
       float y[1][NL];
       y[0][0] = root[0];
-      descend_lean<LP, LP - 1, 0, 1>(y, rec, xo, j0, taus, Alds + lcol);
+      if (MODE == kModeStoreY && rec_lds) {
+        // every load is issued before the first store; addresses past the
+        // record are clamped to its last float
+        float v[kRecLds / 64];
+#pragma unroll
+        for (int i = 0; i < kRecLds / 64; ++i) v[i] = rec[min(lane + 64 * i, (int)a.rec - 1)];
+#pragma unroll
+        for (int i = 0; i < kRecLds / 64; ++i) recl[lane + 64 * i] = v[i];
+        descend_lean<LP, LP - 1, 0, 1, true>(y, recl, xo, j0, taus, Alds + lcol);
+      } else {
+        descend_lean<LP, LP - 1, 0, 1>(y, rec, xo, j0, taus, Alds + lcol);
+      }
       if constexpr (MODE == kModeStoreY) {
         if (a.nup > 0 && rho + a.nw < last) root_batch(rho + a.nw, 0, rvn);
 #pragma unroll
@@ -543,8 +564,10 @@ static const void *leaf_fn(const Geometry &G, int mode, int gf, int cpl) {
 }
 
 static size_t leaf_lds_bytes(const Geometry &G, int mode, int cpl, int nw) {
-  return sizeof(float) * kTileT *
-         ((size_t)cpl * (G.jlow + kLdsPadRows) + (mode == kModeGrad ? (size_t)nw * G.jlow : 0));
+  size_t floats = (size_t)kTileT *
+                  ((size_t)cpl * (G.jlow + kLdsPadRows) + (mode == kModeGrad ? (size_t)nw * G.jlow : 0));
+  if (mode == kModeStoreY && G.rec <= kRecLds) floats += (size_t)nw * kRecSlot;
+  return sizeof(float) * floats;
 }
 
 // Workgroups of a kernel instance that fit on the current device at once.

@@ -37,7 +37,23 @@ __device__ __forceinline__ void keep_scalar(const float (&v)[N]) {
   for (int i = 0; i < N; ++i) asm volatile("" ::"s"(v[i]));
 }
 
-template <int LP, int L, int LAST, int CPL>
+// A point value of the record: from global memory through the scalar cache,
+// or (VX) from the wave's LDS copy, moved to a scalar register, so that a
+// batch occupies scalar registers only in either case.
+template <bool VX>
+__device__ __forceinline__ float ldx(const float *__restrict__ x, int i) {
+  if constexpr (VX) return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x[i])));
+  else return x[i];
+}
+
+// Records of at most kRecLds floats can be copied to a per-wave LDS slot
+// (storing and per-point modes); the slot has room for the descent's reads
+// past a level's block.
+constexpr int kRecLds = 512;
+constexpr int kRecSlot = kRecLds + kBatchFloats;
+
+// VX: the record is in LDS (see ldx).
+template <int LP, int L, int LAST, int CPL, bool VX = false>
 __device__ __forceinline__ void descend_lean(float (&y)[CPL][1 << LP], const float *__restrict__ rec,
                                              int &xo, int &j0, uint64_t taus, const float *Al) {
   if constexpr (L >= LAST) {
@@ -59,7 +75,7 @@ __device__ __forceinline__ void descend_lean(float (&y)[CPL][1 << LP], const flo
         // first batch: coordinate 0 forms the children (the tile step)
         float xs[B * NC], av[B][CPL];
 #pragma unroll
-        for (int i = 0; i < B * NC; ++i) xs[i] = x[i];
+        for (int i = 0; i < B * NC; ++i) xs[i] = ldx<VX>(x, i);
 #pragma unroll
         for (int i = 0; i < B; ++i)
 #pragma unroll
@@ -88,7 +104,7 @@ __device__ __forceinline__ void descend_lean(float (&y)[CPL][1 << LP], const flo
 #pragma unroll 1
         for (int jb = B; jb < tau; jb += B) {
 #pragma unroll
-          for (int i = 0; i < B * NC; ++i) xs[i] = x[jb * NC + i];
+          for (int i = 0; i < B * NC; ++i) xs[i] = ldx<VX>(x, jb * NC + i);
 #pragma unroll
           for (int i = 0; i < B; ++i)
 #pragma unroll
@@ -116,14 +132,14 @@ __device__ __forceinline__ void descend_lean(float (&y)[CPL][1 << LP], const flo
 #pragma unroll
         for (int q = 0; q < CPL; ++q) a[q] = Aj[q * kTileT];
 #pragma unroll
-        for (int i = 0; i < H; ++i) xs[i] = x[H + i];
+        for (int i = 0; i < H; ++i) xs[i] = ldx<VX>(x, H + i);
         keep_scalar(xs);
 #pragma unroll
         for (int q = 0; q < CPL; ++q)
 #pragma unroll
           for (int c = 0; c < H; ++c) y[q][c + H] = fmaf(xs[c], a[q], y[q][c]);
 #pragma unroll
-        for (int i = 0; i < H; ++i) xs[i] = x[i];
+        for (int i = 0; i < H; ++i) xs[i] = ldx<VX>(x, i);
         keep_scalar(xs);
 #pragma unroll
         for (int q = 0; q < CPL; ++q)
@@ -136,7 +152,7 @@ __device__ __forceinline__ void descend_lean(float (&y)[CPL][1 << LP], const flo
 #pragma unroll
           for (int h = 0; h < 2; ++h) {
 #pragma unroll
-            for (int i = 0; i < H; ++i) xs[i] = x[jj * NC + h * H + i];
+            for (int i = 0; i < H; ++i) xs[i] = ldx<VX>(x, jj * NC + h * H + i);
             keep_scalar(xs);
 #pragma unroll
             for (int q = 0; q < CPL; ++q)
@@ -147,7 +163,7 @@ __device__ __forceinline__ void descend_lean(float (&y)[CPL][1 << LP], const flo
       }
       xo += tau * NC;
     }
-    descend_lean<LP, L - 1, LAST, CPL>(y, rec, xo, j0, taus, Al);
+    descend_lean<LP, L - 1, LAST, CPL, VX>(y, rec, xo, j0, taus, Al);
   }
 }
 
