@@ -399,8 +399,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
       }
       if constexpr (MODE == kModeStoreY) {
         if (a.nup > 0 && rho + a.nw < last) root_batch(rho + a.nw, 0, rvn);
+        // Y is streamed past the caches (it is not read back here, and a large
+        // one would only evict the records and root rows)
 #pragma unroll
-        for (int c = 0; c < NL; ++c) Y[((int64_t)rho + (int64_t)c * a.nsub) * a.ldy + ct * CW + lcol] = y[0][c];
+        for (int c = 0; c < NL; ++c)
+          __builtin_nontemporal_store(y[0][c], &Y[((int64_t)rho + (int64_t)c * a.nsub) * a.ldy + ct * CW + lcol]);
       } else {
         float v[64];
 #pragma unroll
