@@ -22,7 +22,10 @@
 //   Sum    sum_k sum_i g(y_ki): FP32 inside a subtree, FP64 across subtrees;
 //          one FP64 partial per workgroup (reduced in a fixed order afterwards)
 //   Point  per-point sums over the wave's 64 columns (for non-separable h)
-//   StoreY write y_ki (the matrix-vector product)
+//   StoreY write y_ki (the matrix-vector product): the subtree's record is
+//          first copied to a per-wave LDS slot (one round of vector loads)
+//          when it has at most kRecLds floats, the workgroups are taken
+//          column tile first, and Y is written with non-temporal stores
 //   Grad   G'_ki = h'(u_k) g'_unit(y_ki); sums of G' up the subtree give S_I
 //          for the lower levels (the transpose of the recursion), dA_I +=
 //          X~_I^T S_I, the subtree-root sums S_{L'} go to memory.  This file

@@ -183,14 +183,18 @@ __device__ __forceinline__ double ppnd16(double p) {
   return q < 0.0 ? -v : v;
 }
 
-template <bool INVNORM, int VB = 0>
+// IIDK: the point set is known to be reduced Monte Carlo, so the other kinds'
+// code (and registers) is left out.
+template <bool INVNORM, int VB = 0, bool IIDK = false>
 __device__ __forceinline__ double value_f64(const PointConsts &G, const DevSpec &D, int r, int j,
                                             uint32_t rho, int nb) {
   double x;
-  if (G.kind == QMC_IID) {
+  if (IIDK || G.kind == QMC_IID) {
     // reduced Monte Carlo (Section 4, eq. randpts): the distinct values of
     // coordinate j are its own i.i.d. samples, point k taking sample k mod n_j
     x = D.samples[(size_t)r * D.sample_total + D.soff[j] + rho];
+  } else if constexpr (IIDK) {
+    x = 0.0;  // not reached
   } else if (VB == 0 && G.rand == QMC_DIGITAL_SHIFT) {
     const uint32_t c = value_int<0>(G, D.gen, j, rho, nb);
     const uint64_t U = ((uint64_t)c << (52 - nb)) ^ D.dshift[(size_t)r * G.s + j];
@@ -268,8 +272,12 @@ struct TabArgs {
 template <bool INVNORM>
 constexpr int vals_per_thread() { return INVNORM ? 2 : 8; }
 
-template <bool INVNORM>
-__global__ __launch_bounds__(256) void tables_kernel(TabArgs ta, DevSpec D, int r0,
+// The inverse normal map asks for eight waves per SIMD: left free, the compiler
+// interleaves the FP64 evaluations of a thread's values into about 126
+// registers (four waves); at 64 nothing spills.
+template <bool INVNORM, bool IIDK>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(INVNORM ? 8 : 1))) void tables_kernel(
+    TabArgs ta, DevSpec D, int r0,
                                                      float *__restrict__ out,
                                                      uint32_t *__restrict__ counters, int ncounters) {
   constexpr int VPT = vals_per_thread<INVNORM>();
@@ -308,7 +316,7 @@ __global__ __launch_bounds__(256) void tables_kernel(TabArgs ta, DevSpec D, int 
     float val[VPT];
 #pragma unroll
     for (int v = 0; v < VPT; ++v)
-      val[v] = (float)value_f64<INVNORM>(ta.G, D, r0 + rl, (int)jv[v], rho[v], sg.nb);
+      val[v] = (float)value_f64<INVNORM, 0, IIDK>(ta.G, D, r0 + rl, (int)jv[v], rho[v], sg.nb);
 #pragma unroll
     for (int v = 0; v < VPT; ++v)
       if (base + 256u * v < sg.count) o_r[dst[v]] = val[v];
@@ -392,10 +400,15 @@ hipError_t launch_tables(const Geometry &G, const DevSpec &D, int r0, int nr, fl
   ta.nblk = total;
   if (total == 0) total = 1;  // still zero the counters
   dim3 grid(total, nr);
-  if (G.map == QMC_MAP_INVNORM)
-    hipLaunchKernelGGL(tables_kernel<true>, grid, dim3(256), 0, st, ta, D, r0, out, counters, ncounters);
+  const bool iid = G.kind == QMC_IID;
+  if (G.map == QMC_MAP_INVNORM && iid)
+    hipLaunchKernelGGL((tables_kernel<true, true>), grid, dim3(256), 0, st, ta, D, r0, out, counters, ncounters);
+  else if (G.map == QMC_MAP_INVNORM)
+    hipLaunchKernelGGL((tables_kernel<true, false>), grid, dim3(256), 0, st, ta, D, r0, out, counters, ncounters);
+  else if (iid)
+    hipLaunchKernelGGL((tables_kernel<false, true>), grid, dim3(256), 0, st, ta, D, r0, out, counters, ncounters);
   else
-    hipLaunchKernelGGL(tables_kernel<false>, grid, dim3(256), 0, st, ta, D, r0, out, counters, ncounters);
+    hipLaunchKernelGGL((tables_kernel<false, false>), grid, dim3(256), 0, st, ta, D, r0, out, counters, ncounters);
   return hipGetLastError();
 }
 
