@@ -270,7 +270,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
   // own LDS slot with one round of vector loads, and the descent reads its
   // point values there instead of in one scalar round trip per batch.
   float *recl = smem + (jlow + kLdsPadRows) * CW + w * kRecSlot;
-  const bool rec_lds = MODE == kModeStoreY && a.rec <= kRecLds;
+  const bool rec_lds = MODE == kModeStoreY && a.rec >= 1 && a.rec <= kRecLds;  // split 0: no record
   if (MODE == kModeGrad)
     for (int e = lane; e < jlow * kTileT; e += 64) dAl[e] = 0.f;
   __syncthreads();
@@ -572,7 +572,7 @@ static const void *leaf_fn(const Geometry &G, int mode, int gf, int cpl) {
 static size_t leaf_lds_bytes(const Geometry &G, int mode, int cpl, int nw) {
   size_t floats = (size_t)kTileT *
                   ((size_t)cpl * (G.jlow + kLdsPadRows) + (mode == kModeGrad ? (size_t)nw * G.jlow : 0));
-  if (mode == kModeStoreY && G.rec <= kRecLds) floats += (size_t)nw * kRecSlot;
+  if (mode == kModeStoreY && G.rec >= 1 && G.rec <= kRecLds) floats += (size_t)nw * kRecSlot;
   return sizeof(float) * floats;
 }
 

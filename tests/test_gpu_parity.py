@@ -127,6 +127,21 @@ def test_matvec_shapes(split_case):
     _check_Y(wl, Y, 0, I.FP32)
 
 
+def test_split_level_zero():
+    """More than 64 coordinates in level 0 leave no lower levels (split level
+    0: every level, level 0 included, is an upper-level product and a subtree
+    is one point): Y element by element, Q, and dQ/dA element by element."""
+    torch = torch_cuda()
+    wl = small(I.LATTICE, I.RANDOM_SHIFT, m=6, s=70, t=65, w=[0] * 66 + [1, 2, 3, 7], R=2)
+    pts = q.Points.from_workload(wl)
+    assert pts.split_level == 0 and pts.grad_split_level == 0
+    A = to_dev(wl.A, torch)
+    for r in range(wl.R):
+        Y = q.reduced_matvec(pts, A, r=r).cpu().numpy()
+        _check_Y(wl, Y, r, I.FP32)
+    _check_grad(wl, pts)
+
+
 def test_matvec_identity_is_point_matrix():
     """A = I_s gives Y = X exactly (FP32 path)."""
     torch = torch_cuda()
