@@ -187,9 +187,24 @@ __device__ __forceinline__ void ascend_all(float (&S)[1 << LP], const float *__r
 // lane l holds sum over lanes of v[l] (butterfly transpose-reduction: at
 // distance D a lane keeps the half of its slots selected by bit D of its
 // lane id and adds the partner's copy of those slots).
+// At distances 32 and 16 one lane-swap instruction does the exchange:
+// v_permlane32_swap(X, Y) returns (X of lanes 0-31, Y of lanes 0-31) and
+// (X of lanes 32-63, Y of lanes 32-63) as the lower and upper halves of its
+// two results (v_permlane16_swap the same for 16-lane rows), so each lane's
+// kept slot and its partner's copy are the two results, and one add finishes
+// the pair (the same sums as the selected exchange below, bit for bit).
 template <int D>
 __device__ __forceinline__ void transpose_step(float (&v)[64], int lane) {
-  if constexpr (D >= 1) {
+  if constexpr (D == 32 || D == 16) {
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      const auto r = D == 32
+                         ? __builtin_amdgcn_permlane32_swap(__float_as_uint(v[c]), __float_as_uint(v[c + D]), false, false)
+                         : __builtin_amdgcn_permlane16_swap(__float_as_uint(v[c]), __float_as_uint(v[c + D]), false, false);
+      v[c] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
+    transpose_step<D / 2>(v, lane);
+  } else if constexpr (D >= 1) {
     const bool hi = (lane & D) != 0;
 #pragma unroll
     for (int c = 0; c < D; ++c) {
