@@ -4,6 +4,8 @@
 // subtree record and the meaning of the descent.
 #pragma once
 
+#include <type_traits>
+
 #include "qmc_internal.h"
 
 namespace qmc {
@@ -93,16 +95,19 @@ __device__ __forceinline__ void descend_lean(float (&y)[CPL][1 << LP], const flo
 #pragma unroll
           for (int c = 0; c < H; ++c) y[q][c] = fmaf(xs[c], av[0][q], y[q][c]);
         }
+        // batches that hold B coordinates need no per-coordinate check; only
+        // a last, partial one does
+        auto madd = [&](int jb, int i0, auto checked) {
 #pragma unroll
-        for (int i = 1; i < B; ++i) {
-          if (i >= tau) break;
+          for (int i = i0; i < B; ++i) {
+            if (decltype(checked)::value && jb + i >= tau) break;
 #pragma unroll
-          for (int q = 0; q < CPL; ++q)
+            for (int q = 0; q < CPL; ++q)
 #pragma unroll
-            for (int c = 0; c < NC; ++c) y[q][c] = fmaf(xs[i * NC + c], av[i][q], y[q][c]);
-        }
-#pragma unroll 1
-        for (int jb = B; jb < tau; jb += B) {
+              for (int c = 0; c < NC; ++c) y[q][c] = fmaf(xs[i * NC + c], av[i][q], y[q][c]);
+          }
+        };
+        auto fetch = [&](int jb) {
 #pragma unroll
           for (int i = 0; i < B * NC; ++i) xs[i] = ldx<VX>(x, jb * NC + i);
 #pragma unroll
@@ -114,14 +119,18 @@ __device__ __forceinline__ void descend_lean(float (&y)[CPL][1 << LP], const flo
           for (int i = 0; i < B; ++i)
 #pragma unroll
             for (int q = 0; q < CPL; ++q) asm volatile("" ::"v"(av[i][q]));
-#pragma unroll
-          for (int i = 0; i < B; ++i) {
-            if (jb + i >= tau) break;
-#pragma unroll
-            for (int q = 0; q < CPL; ++q)
-#pragma unroll
-              for (int c = 0; c < NC; ++c) y[q][c] = fmaf(xs[i * NC + c], av[i][q], y[q][c]);
-          }
+        };
+        if (tau >= B) madd(0, 1, std::false_type{});
+        else madd(0, 1, std::true_type{});
+        int jb = B;
+#pragma unroll 1
+        for (; jb + B <= tau; jb += B) {
+          fetch(jb);
+          madd(jb, 0, std::false_type{});
+        }
+        if (jb < tau) {
+          fetch(jb);
+          madd(jb, 0, std::true_type{});
         }
       } else {
         // NC = 64 (level 0 with more than one coordinate): one coordinate at a
